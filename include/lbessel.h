@@ -1,0 +1,180 @@
+/*
+ * lbessel: log I_v(x) and log K_v(x) of the modified Bessel functions over
+ * device arrays, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Plesner, Sorensen, Hauberg, "Accurate Computation of the Logarithm
+ * of Modified Bessel Functions on GPUs" (arXiv 2409.08729).  Each element is
+ * evaluated by one of three branches chosen from (v, x) alone (Sec.
+ * "Algorithms", Table 1 and Algorithm 1 in its GPU form): the Hankel
+ * expansion with 20 correction terms (eqs. log Iv mu k / log Kv mu k), the
+ * Debye expansion with 13 terms (eqs. log Iv u k / log Kv u k), or, for small
+ * arguments, the power series of I_v (eqs. Iv infinite series, log Iv) or the
+ * integral representation of K_v (eq. log Kv integral).  All intermediate
+ * quantities stay on a log scale, so results are finite wherever log I_v(x)
+ * and log K_v(x) are.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named v, x, gout, kappa, out, gx are DEVICE pointers owned by
+ *    the caller, each to n contiguous elements (kappa: n, v/x: n).  Outputs
+ *    must not overlap inputs.  The library allocates nothing and keeps no
+ *    state between calls; calls are safe from several host threads.
+ *  - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *    Every call only enqueues work on that stream and returns; the caller
+ *    synchronises before reading out.
+ *  - n may be 0 (nothing is launched).  n < 0, or a NULL pointer with n > 0,
+ *    is an API error.
+ *  - Return value: LBESSEL_OK (0), or a negative LBESSEL_E* code; nothing is
+ *    enqueued when an error is returned.
+ *  - Domain problems are per-element values, never error codes:
+ *      log I_v(x): v < 0 or x < 0 -> NaN;  x = 0 -> 0 if v = 0 else -inf;
+ *                  x = +inf -> +inf;  v = +inf -> -inf;  NaN -> NaN.
+ *      log K_v(x): evaluated at |v| (K_{-v} = K_v);  x < 0 -> NaN;
+ *                  x = 0 -> +inf;  x = +inf -> -inf;  |v| = inf -> +inf;
+ *                  NaN -> NaN.
+ *    (The paper states the domains v >= 0, x >= 0 for I and real v for K;
+ *    the boundary values are the limits of the functions.)
+ *  - f64 entry points compute in binary64 throughout; f32 entry points take
+ *    and return binary32 and compute in binary32 except where stated.
+ */
+#ifndef LBESSEL_H
+#define LBESSEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBESSEL_OK 0
+#define LBESSEL_EINVAL (-1)   /* NULL pointer with n > 0, n < 0, bad scalar   */
+#define LBESSEL_EHIP (-2)     /* the HIP runtime rejected a launch          */
+#define LBESSEL_ENODEV (-3)   /* no usable gfx950 device is current         */
+
+#define LBESSEL_ABI_VERSION 1
+
+/* ---------------------------------------------------------------------- */
+/* Forward evaluation                                                      */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * out[i] = log I_{v[i]}(x[i]).
+ * Algorithm 1 of the paper in its three-branch GPU form, with re-fitted
+ * branch thresholds (Table 1 shapes).  Elements are grouped by branch inside
+ * each workgroup so a wavefront runs one branch; results do not depend on
+ * neighbouring elements.
+ */
+int lbessel_log_iv_f64(const double *v, const double *x, double *out,
+                       int64_t n, void *stream);
+int lbessel_log_iv_f32(const float *v, const float *x, float *out,
+                       int64_t n, void *stream);
+
+/*
+ * out[i] = log K_{v[i]}(x[i]); same structure, with the integral
+ * representation (eq. log Kv integral) as the small-argument branch.
+ */
+int lbessel_log_kv_f64(const double *v, const double *x, double *out,
+                       int64_t n, void *stream);
+int lbessel_log_kv_f32(const float *v, const float *x, float *out,
+                       int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Derivatives in x (the paper names derivatives as future work)            */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * gx[i] = gout[i] * d/dx log I_v(x) at (v[i], x[i]), using
+ * I_v'(x) = I_{v+1}(x) + (v/x) I_v(x) (DLMF 10.29.2):
+ *   d/dx log I_v(x) = exp(log I_{v+1}(x) - log I_v(x)) + v/x.
+ * Both log-values come from the forward algorithm above.  At x = 0 the
+ * derivative is 0 for v = 0 and +inf for v > 0; at x = +inf it is 1.
+ */
+int lbessel_log_iv_grad_x_f64(const double *v, const double *x,
+                              const double *gout, double *gx, int64_t n,
+                              void *stream);
+int lbessel_log_iv_grad_x_f32(const float *v, const float *x,
+                              const float *gout, float *gx, int64_t n,
+                              void *stream);
+
+/*
+ * gx[i] = gout[i] * d/dx log K_v(x), with K_v' = -K_{v+1} + (v/x) K_v:
+ *   d/dx log K_v(x) = -exp(log K_{v+1}(x) - log K_v(x)) + v/x,  v -> |v|.
+ * At x = 0 the derivative is -inf; at x = +inf it is -1.
+ */
+int lbessel_log_kv_grad_x_f64(const double *v, const double *x,
+                              const double *gout, double *gx, int64_t n,
+                              void *stream);
+int lbessel_log_kv_grad_x_f32(const float *v, const float *x,
+                              const float *gout, float *gx, int64_t n,
+                              void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* von Mises-Fisher log-normaliser (paper, Sec. "Metric learning")          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * out[i] = log C_p(kappa[i]),
+ *   C_p(k) = k^{p/2-1} / ((2 pi)^{p/2} I_{p/2-1}(k)),
+ * the normalising constant of the vMF density on the unit sphere in R^p.
+ * p is a host scalar, p >= 2 (LBESSEL_EINVAL otherwise, also for NaN/inf).
+ * kappa = 0 gives the limit (p/2-1) log 2 + lgamma(p/2) - (p/2) log 2 pi
+ * (the uniform density); kappa < 0 or NaN gives NaN; kappa = +inf -> NaN.
+ */
+int lbessel_vmf_log_norm_f64(const double *kappa, double p, double *out,
+                             int64_t n, void *stream);
+int lbessel_vmf_log_norm_f32(const float *kappa, float p, float *out,
+                             int64_t n, void *stream);
+
+/*
+ * out[i] = d/dkappa log C_p(kappa[i]) = -I_{p/2}(kappa)/I_{p/2-1}(kappa)
+ * = -A_p(kappa), the derivative used for maximum-likelihood fitting of kappa
+ * (paper, eq. kappa estimates); computed as -exp(log I_{p/2} - log I_{p/2-1}).
+ * kappa = 0 gives 0.
+ */
+int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out,
+                                  int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Diagnostics                                                             */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Per-element branch selection, for tests and measurement: branch[i] is
+ * 0 (Hankel, mu_20), 1 (Debye, U_13), 2 (series for I / integral for K) or
+ * 3 (special value resolved without a branch).  kind: 0 = I, 1 = K.
+ * precision: 64 or 32 (the f32 path has its own thresholds); v and x are
+ * read as double or float accordingly.
+ */
+int lbessel_classify(int kind, int precision, const void *v, const void *x,
+                     uint8_t *branch, int64_t n, void *stream);
+
+/*
+ * Evaluate every element with one forced branch (0, 1 or 2 as above)
+ * regardless of its regime, f64 only.  Used to validate each branch
+ * against the reference on its own; outside a branch's regime the result is
+ * simply that expansion's value, which may be inaccurate.
+ */
+int lbessel_eval_branch_f64(int kind, int branch, const double *v,
+                            const double *x, double *out, int64_t n,
+                            void *stream);
+
+/*
+ * The same forward evaluation as lbessel_log_{iv,kv}_{f64,f32} but one
+ * element per thread with no regrouping by branch (kind 0 = I, 1 = K;
+ * precision 64 or 32).  Results must equal the grouped kernels bit for bit;
+ * tests use this to check the regrouping, the benchmark to price it.
+ */
+int lbessel_eval_ungrouped(int kind, int precision, const void *v,
+                           const void *x, void *out, int64_t n, void *stream);
+
+/* Static description of a status code. */
+const char *lbessel_status_string(int status);
+
+/* LBESSEL_ABI_VERSION of the built library. */
+int lbessel_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBESSEL_H */

@@ -1,0 +1,242 @@
+"""Python binding of liblbessel (HIP, gfx950).
+
+Argument marshalling only: every function checks its torch tensors, allocates
+the output on the same device and calls the C-ABI entry point of the same
+name on torch's current HIP stream.  All arithmetic runs in the library's
+HIP kernels; there is no CPU path.  If the library is not built, or a tensor
+is not on a GPU, the call raises.
+
+log_iv(v, x), log_kv(v, x)                 log I_v(x), log K_v(x)
+log_iv_grad_x(v, x, g), log_kv_grad_x(..)  g * d/dx log I_v(x), log K_v(x)
+vmf_log_norm(kappa, p), vmf_log_norm_grad  log C_p(kappa) and d/dkappa
+LogIv, LogKv                               torch.autograd.Function wrappers
+classify(kind, v, x), eval_branch(...),    diagnostics
+eval_ungrouped(kind, v, x)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbessel.so")
+
+LBESSEL_OK = 0
+KIND = {"I": 0, "K": 1}
+BRANCHES = ("mu20", "u13", "fallback", "special")
+
+_lib = None
+
+
+class LbesselError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LbesselError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2409_08729_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    sig = {
+        "lbessel_log_iv_f64": [vp, vp, vp, i64, vp],
+        "lbessel_log_iv_f32": [vp, vp, vp, i64, vp],
+        "lbessel_log_kv_f64": [vp, vp, vp, i64, vp],
+        "lbessel_log_kv_f32": [vp, vp, vp, i64, vp],
+        "lbessel_log_iv_grad_x_f64": [vp, vp, vp, vp, i64, vp],
+        "lbessel_log_iv_grad_x_f32": [vp, vp, vp, vp, i64, vp],
+        "lbessel_log_kv_grad_x_f64": [vp, vp, vp, vp, i64, vp],
+        "lbessel_log_kv_grad_x_f32": [vp, vp, vp, vp, i64, vp],
+        "lbessel_vmf_log_norm_f64": [vp, ctypes.c_double, vp, i64, vp],
+        "lbessel_vmf_log_norm_f32": [vp, ctypes.c_float, vp, i64, vp],
+        "lbessel_vmf_log_norm_grad_f64": [vp, ctypes.c_double, vp, i64, vp],
+        "lbessel_classify": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_eval_branch_f64": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_eval_ungrouped": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_abi_version": [],
+        "lbessel_status_string": [ctypes.c_int],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.lbessel_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def lib():
+    """The loaded ctypes handle (raises if the library is not built)."""
+    return _load()
+
+
+def _check(status: int, name: str) -> None:
+    if status != LBESSEL_OK:
+        msg = _load().lbessel_status_string(status).decode()
+        raise LbesselError(f"{name} failed: {msg} ({status})")
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _prep(*ts: torch.Tensor):
+    t0 = ts[0]
+    if not isinstance(t0, torch.Tensor) or not t0.is_cuda:
+        raise LbesselError("inputs must be torch tensors on a GPU (there is no CPU path)")
+    if t0.dtype not in (torch.float64, torch.float32):
+        raise LbesselError(f"unsupported dtype {t0.dtype}: float64 or float32 only")
+    out = []
+    for t in ts:
+        if not isinstance(t, torch.Tensor) or t.device != t0.device or t.dtype != t0.dtype:
+            raise LbesselError("all tensors must share one GPU device and one dtype")
+        if t.shape != t0.shape:
+            raise LbesselError(f"shape mismatch: {tuple(t.shape)} vs {tuple(t0.shape)}")
+        out.append(t.contiguous())
+    return out
+
+
+def _suffix(t: torch.Tensor) -> str:
+    return "f64" if t.dtype == torch.float64 else "f32"
+
+
+def _unary(name: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    v, x = _prep(v, x)
+    out = torch.empty_like(x)
+    fn = f"{name}_{_suffix(x)}"
+    with torch.cuda.device(x.device):
+        _check(getattr(_load(), fn)(v.data_ptr(), x.data_ptr(), out.data_ptr(), x.numel(),
+                                    _stream(x)), fn)
+    return out
+
+
+def log_iv(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """log I_v(x), elementwise, float64 or float32."""
+    return _unary("lbessel_log_iv", v, x)
+
+
+def log_kv(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """log K_v(x), elementwise, float64 or float32."""
+    return _unary("lbessel_log_kv", v, x)
+
+
+def _grad(name: str, v, x, g):
+    v, x, g = _prep(v, x, g)
+    out = torch.empty_like(x)
+    fn = f"{name}_{_suffix(x)}"
+    with torch.cuda.device(x.device):
+        _check(getattr(_load(), fn)(v.data_ptr(), x.data_ptr(), g.data_ptr(), out.data_ptr(),
+                                    x.numel(), _stream(x)), fn)
+    return out
+
+
+def log_iv_grad_x(v, x, g=None):
+    """g * d/dx log I_v(x) (g defaults to ones)."""
+    if g is None:
+        g = torch.ones_like(x)
+    return _grad("lbessel_log_iv_grad_x", v, x, g)
+
+
+def log_kv_grad_x(v, x, g=None):
+    """g * d/dx log K_v(x) (g defaults to ones)."""
+    if g is None:
+        g = torch.ones_like(x)
+    return _grad("lbessel_log_kv_grad_x", v, x, g)
+
+
+def vmf_log_norm(kappa: torch.Tensor, p: float) -> torch.Tensor:
+    """log C_p(kappa) of the von Mises-Fisher distribution on S^{p-1}."""
+    (k,) = _prep(kappa)
+    out = torch.empty_like(k)
+    fn = f"lbessel_vmf_log_norm_{_suffix(k)}"
+    with torch.cuda.device(k.device):
+        _check(getattr(_load(), fn)(k.data_ptr(), float(p), out.data_ptr(), k.numel(),
+                                    _stream(k)), fn)
+    return out
+
+
+def vmf_log_norm_grad(kappa: torch.Tensor, p: float) -> torch.Tensor:
+    """d/dkappa log C_p(kappa) = -I_{p/2}(kappa) / I_{p/2-1}(kappa) (float64)."""
+    (k,) = _prep(kappa)
+    if k.dtype != torch.float64:
+        raise LbesselError("vmf_log_norm_grad is float64 only")
+    out = torch.empty_like(k)
+    with torch.cuda.device(k.device):
+        _check(_load().lbessel_vmf_log_norm_grad_f64(k.data_ptr(), float(p), out.data_ptr(),
+                                                     k.numel(), _stream(k)),
+               "lbessel_vmf_log_norm_grad_f64")
+    return out
+
+
+def classify(kind: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Branch index per element (0 mu20, 1 u13, 2 fallback, 3 special)."""
+    v, x = _prep(v, x)
+    out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    prec = 64 if x.dtype == torch.float64 else 32
+    with torch.cuda.device(x.device):
+        _check(_load().lbessel_classify(KIND[kind], prec, v.data_ptr(), x.data_ptr(),
+                                        out.data_ptr(), x.numel(), _stream(x)),
+               "lbessel_classify")
+    return out
+
+
+def eval_branch(kind: str, branch: int, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Every element through one forced branch (float64)."""
+    v, x = _prep(v, x)
+    if x.dtype != torch.float64:
+        raise LbesselError("eval_branch is float64 only")
+    out = torch.empty_like(x)
+    with torch.cuda.device(x.device):
+        _check(_load().lbessel_eval_branch_f64(KIND[kind], int(branch), v.data_ptr(),
+                                               x.data_ptr(), out.data_ptr(), x.numel(),
+                                               _stream(x)), "lbessel_eval_branch_f64")
+    return out
+
+
+def eval_ungrouped(kind: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Forward evaluation without regrouping by branch (one element per thread)."""
+    v, x = _prep(v, x)
+    out = torch.empty_like(x)
+    prec = 64 if x.dtype == torch.float64 else 32
+    with torch.cuda.device(x.device):
+        _check(_load().lbessel_eval_ungrouped(KIND[kind], prec, v.data_ptr(), x.data_ptr(),
+                                              out.data_ptr(), x.numel(), _stream(x)),
+               "lbessel_eval_ungrouped")
+    return out
+
+
+class LogIv(torch.autograd.Function):
+    """log I_v(x) with the hand-written d/dx backward (no gradient in v)."""
+
+    @staticmethod
+    def forward(ctx, v, x):
+        ctx.save_for_backward(v, x)
+        return log_iv(v, x)
+
+    @staticmethod
+    def backward(ctx, g):
+        v, x = ctx.saved_tensors
+        if ctx.needs_input_grad[0]:
+            raise LbesselError("the derivative in the order v is not provided")
+        return None, log_iv_grad_x(v, x, g.contiguous())
+
+
+class LogKv(torch.autograd.Function):
+    """log K_v(x) with the hand-written d/dx backward (no gradient in v)."""
+
+    @staticmethod
+    def forward(ctx, v, x):
+        ctx.save_for_backward(v, x)
+        return log_kv(v, x)
+
+    @staticmethod
+    def backward(ctx, g):
+        v, x = ctx.saved_tensors
+        if ctx.needs_input_grad[0]:
+            raise LbesselError("the derivative in the order v is not provided")
+        return None, log_kv_grad_x(v, x, g.contiguous())

@@ -1,0 +1,319 @@
+// Device math for log I_v(x) and log K_v(x) on gfx950.
+//
+// Branches follow Plesner, Sorensen, Hauberg, arXiv 2409.08729:
+//   mu_20 : Hankel expansion with 20 correction terms, eqs. (log Iv mu k),
+//           (log Kv mu k);
+//   U_13  : Debye expansion with 13 terms, eqs. (log Iv u k), (log Kv u k),
+//           u_k(t) from eqs. (u0), (uk);
+//   series: power series of I_v summed in log scale, eqs. (Iv infinite
+//           series), (ak recurrence), (log Iv), truncated when the remaining
+//           terms fall below the working precision (text after eq. K);
+//   quad  : integral representation of K_v (eq. log Kv integral, n = 8) on
+//           the paper's N = 600 equispaced nodes, summed in log scale with
+//           the heuristic maxima u* = 1 for g and u* = 1/2 or 1/(2v) for h.
+// Branch selection keeps the predicate shapes of Table 1 / Algorithm 1 (GPU
+// form: mu_20, then U_13, else the fallback) with thresholds re-fitted so
+// that each branch meets 1e-15 relative error on its region.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbessel_tables.h"
+
+namespace lbessel {
+
+enum : int { KIND_I = 0, KIND_K = 1 };
+enum : int { BR_MU = 0, BR_U = 1, BR_FB = 2, BR_NONE = 3 };
+
+// ---------------------------------------------------------------------------
+// Constant tables
+// ---------------------------------------------------------------------------
+// Coefficient tables are read through a pointer the optimiser cannot see
+// through, in the constant address space: the loads become scalar loads at
+// their point of use instead of ~200 registers of constants hoisted out of
+// the evaluation loop of the grouped kernel.
+#define LB_CONST_AS __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const LB_CONST_AS T *opaque_const(const T *p) {
+    const LB_CONST_AS T *q = (const LB_CONST_AS T *)p;
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Constants
+// ---------------------------------------------------------------------------
+
+template <typename T> struct Cst;
+template <> struct Cst<double> {
+    static constexpr double log_2pi = 0x1.d67f1c864beb5p+0;      // log(2 pi)
+    static constexpr double log_pi_2 = 0x1.ce6bb25aa1316p-2;     // log(pi/2)
+    static constexpr double half_log_pi = 0x1.250d048e7a1bdp-1;  // log(pi)/2
+    static constexpr double log_n = 0x1.99674ba3fdd16p+2;        // log(600)
+    static constexpr double ln2 = 0x1.62e42fefa39efp-1;
+    static constexpr double series_eps = 0x1p-56;  // relative truncation
+    static constexpr double big_z = 1e150;         // sqrt(1+z^2) == z beyond
+};
+template <> struct Cst<float> {
+    static constexpr float log_2pi = 0x1.d67f1cp+0f;
+    static constexpr float log_pi_2 = 0x1.ce6bb2p-2f;
+    static constexpr float half_log_pi = 0x1.250d04p-1f;
+    static constexpr float log_n = 0x1.99674cp+2f;
+    static constexpr float ln2 = 0x1.62e430p-1f;
+    static constexpr float series_eps = 0x1p-27f;
+    static constexpr float big_z = 1e18f;
+};
+
+// Regime thresholds.  Shapes of Table 1:
+//   mu_20 : (x > x1 && v < v1) || (v^2 < c x && x > x2)
+//   U_13  : (x > x3 && v > v3) || (v > v4)
+// The second mu clause is the paper's (a log x + b > log v) with a = 1/2,
+// written without logarithms: v^2 < e^{2b} x, here e^{2b} = e^{1.4}.
+struct RegimeSet {
+    double x1, v1, c, x2, x3, v3, v4;
+};
+// binary64 sets: every branch within 1e-15 (relative to max(|y|, 1 + |(v, x)|))
+// of the reference on its region.
+template <typename T, int KIND> struct Regime;
+template <> struct Regime<double, KIND_I> {
+    static constexpr RegimeSet r = {21.5, 8.5, 0x1.0388657115a47p+2, 24.0, 23.0, 0.1, 14.5};
+};
+template <> struct Regime<double, KIND_K> {
+    static constexpr RegimeSet r = {17.5, 8.5, 0x1.0388657115a47p+2, 17.5, 20.0, 0.1, 14.5};
+};
+// binary32 uses the binary64 regions (its fallback branch is evaluated in
+// binary64, the asymptotic ones in binary32).
+template <> struct Regime<float, KIND_I> {
+    static constexpr RegimeSet r = Regime<double, KIND_I>::r;
+};
+template <> struct Regime<float, KIND_K> {
+    static constexpr RegimeSet r = Regime<double, KIND_K>::r;
+};
+
+// ---------------------------------------------------------------------------
+// Special values and branch choice
+// ---------------------------------------------------------------------------
+
+// Returns true (and sets *y) when (v, x) is outside the region the branches
+// handle: NaN, negative, zero or infinite arguments.  For K, v is |v|.
+template <typename T, int KIND>
+__device__ __forceinline__ bool special_value(T v, T x, T *y) {
+    const T inf = __builtin_huge_val();
+    const T nan = __builtin_nan("");
+    if (KIND == KIND_I) {
+        if (!(v >= T(0)) || !(x >= T(0))) { *y = nan; return true; }   // NaN or < 0
+        if (v == inf) { *y = (x == inf) ? nan : -inf; return true; }
+        if (x == T(0)) { *y = (v == T(0)) ? T(0) : -inf; return true; }
+        if (x == inf) { *y = inf; return true; }
+        return false;
+    } else {
+        if (!(x >= T(0)) || v != v) { *y = nan; return true; }
+        if (v == inf) { *y = (x == inf || x == T(0)) ? nan : inf; return true; }
+        if (x == T(0)) { *y = inf; return true; }
+        if (x == inf) { *y = -inf; return true; }
+        return false;
+    }
+}
+
+template <typename T, int KIND>
+__device__ __forceinline__ int classify(T v, T x) {
+    constexpr RegimeSet r = Regime<T, KIND>::r;
+    const bool mu = (x > T(r.x1) && v < T(r.v1)) || (v * v < T(r.c) * x && x > T(r.x2));
+    const bool u = (x > T(r.x3) && v > T(r.v3)) || (v > T(r.v4));
+    return mu ? BR_MU : (u ? BR_U : BR_FB);
+}
+
+// ---------------------------------------------------------------------------
+// mu_20: Hankel expansion
+// ---------------------------------------------------------------------------
+// S = 1 + sum_{k=1}^{20} c_k,  c_k = c_{k-1} (mu - (2k-1)^2) s / (8 k x),
+// s = -1 for I (alternating), +1 for K; mu = 4 v^2.
+template <typename T> __device__ __forceinline__ const T (*hankel_table())[2];
+template <> __device__ __forceinline__ const double (*hankel_table<double>())[2] {
+    return tables::kHankel64;
+}
+template <> __device__ __forceinline__ const float (*hankel_table<float>())[2] {
+    return tables::kHankel32;
+}
+
+template <typename T, int KIND>
+__device__ __forceinline__ T br_mu20(T v, T x) {
+    const T mu = T(4) * v * v;
+    const T q = (KIND == KIND_I ? T(-0.125) : T(0.125)) / x;
+    const LB_CONST_AS T *hk = opaque_const<T>(&hankel_table<T>()[0][0]);
+    T c = T(1);
+    T s = T(0);
+#pragma unroll
+    for (int k = 1; k <= tables::kMuTerms; ++k) {
+        // (mu - (2k-1)^2) / k = fma(mu, 1/k, -(2k-1)^2/k)
+        const T d = fma(mu, hk[2 * (k - 1)], -hk[2 * (k - 1) + 1]);
+        c = c * d * q;
+        s = s + c;
+    }
+    const T ls = log(fabs(T(1) + s));
+    if (KIND == KIND_I)
+        return x - T(0.5) * (Cst<T>::log_2pi + log(x)) + ls;
+    else
+        return T(0.5) * (Cst<T>::log_pi_2 - log(x)) - x + ls;
+}
+
+// ---------------------------------------------------------------------------
+// U_13: Debye expansion
+// ---------------------------------------------------------------------------
+// z = x/v, r = sqrt(1+z^2), t = 1/r, eta = r + log(z/(1+r)),
+// S = 1 + sum_k (+-1)^k u_k(t) / v^k = 1 + sum_k w^k P_k(t^2), w = +-t/v
+// (u_k(t) = t^k P_k(t^2)).  The -1/2 log(2 pi v) - 1/4 log(1+z^2) terms are
+// merged into -1/2 log(2 pi v r).
+template <typename T> __device__ __forceinline__ const T (*debye_table())[14];
+template <> __device__ __forceinline__ const double (*debye_table<double>())[14] {
+    return tables::kDebyeP64;
+}
+template <> __device__ __forceinline__ const float (*debye_table<float>())[14] {
+    return tables::kDebyeP32;
+}
+
+template <typename T, int KIND>
+__device__ __forceinline__ T br_u13(T v, T x) {
+    const T z = x / v;
+    const T r = (z < Cst<T>::big_z) ? sqrt(fma(z, z, T(1))) : z;
+    const T t = T(1) / r;
+    const T p = t * t;
+    const T w = (KIND == KIND_I ? t : -t) / v;
+    const LB_CONST_AS T *P = opaque_const<T>(&debye_table<T>()[0][0]);
+    T acc = T(0);
+#pragma unroll
+    for (int k = tables::kUTerms; k >= 1; --k) {
+        const LB_CONST_AS T *row = P + 14 * (k - 1);
+        T pk = row[k];
+#pragma unroll
+        for (int j = k - 1; j >= 0; --j)
+            pk = fma(pk, p, row[j]);
+        acc = w * (pk + acc);
+    }
+    const T eta = r + log(z / (T(1) + r));
+    const T ls = log(fabs(T(1) + acc));
+    const T lvr = log(v * r);
+    if (KIND == KIND_I)
+        return v * eta - T(0.5) * (Cst<T>::log_2pi + lvr) + ls;
+    else
+        return T(0.5) * (Cst<T>::log_pi_2 - lvr) - v * eta + ls;
+}
+
+// ---------------------------------------------------------------------------
+// Series for I_v (fallback of I)
+// ---------------------------------------------------------------------------
+// log I = v log(x/2) - lgamma(v+1) + log sum_k a_k/a_0,
+// a_k/a_{k-1} = (x/2)^2 / (k (k+v)).  On this branch's region (v < 14.5,
+// x <= 23) every ratio a_k/a_0 stays below 1e16, so the log-sum shift by the
+// first term cannot overflow.  The sum stops once the current ratio is below
+// 1/2 (all later ones are smaller) and the term is below eps * sum, which
+// bounds the dropped tail by 2 eps relative.
+template <typename T>
+__device__ __forceinline__ T br_series_i(T v, T x) {
+    const T hx = T(0.5) * x;
+    const T q = hx * hx;
+    T term = T(1);
+    T sum = T(1);
+    for (int k = 1; k < 200; ++k) {
+        const T fk = T(k);
+        const T den = fk * (fk + v);
+        term = term * q / den;
+        sum = sum + term;
+        if (den > T(2) * q && term < Cst<T>::series_eps * sum)
+            break;
+    }
+    return v * log(hx) - lgamma(v + T(1)) + log(sum);
+}
+
+// ---------------------------------------------------------------------------
+// Integral for K_v (fallback of K)
+// ---------------------------------------------------------------------------
+// log K = 1/2 log pi - lgamma(v+1/2) - v log 2x - x + log int_0^1 (g + h) du,
+//   g(u) = beta exp(-u^beta) (2x + u^beta)^{v-1/2} u^{n-1},  beta = 2n/(2v+1),
+//   h(u) = exp(-1/u) u^{-2v-1} (2xu + 1)^{v-1/2},            n = 8.
+// Nodes u_j = j/600 (g(0) = h(0) = 0); weights: trapezoid with a Gregory
+// end correction of order 8 at u = 1.  Each term is exponentiated relative to
+// the heuristic maximum of its function, log g(1) and log h(u*), written as
+// log-ratios so that no large intermediate cancels:
+//   log g(u) - log g(1)  = (1 - u^b) + (v - 1/2) log((2x + u^b)/(2x + 1)) + 7 log u
+//   log h(u) - log h(u*) = (1/u* - 1/u) - (2v+1) log(u/u*)
+//                          + (v - 1/2) log((2xu + 1)/(2xu* + 1)).
+template <typename T> __device__ __forceinline__ const T (*quad_nodes())[3];
+template <> __device__ __forceinline__ const double (*quad_nodes<double>())[3] {
+    return tables::kQuadNode64;
+}
+template <> __device__ __forceinline__ const float (*quad_nodes<float>())[3] {
+    return tables::kQuadNode32;
+}
+template <typename T> __device__ __forceinline__ const T *gregory_tail();
+template <> __device__ __forceinline__ const double *gregory_tail<double>() {
+    return tables::kGregoryTail64;
+}
+template <> __device__ __forceinline__ const float *gregory_tail<float>() {
+    return tables::kGregoryTail32;
+}
+
+template <typename T>
+__device__ __forceinline__ T br_quad_k(T v, T x) {
+    constexpr int N = tables::kQuadN;
+    constexpr int NT = tables::kGregoryOrder + 1;   // nodes with weight != 1
+    const T beta = T(16) / (T(2) * v + T(1));
+    const T vm = v - T(0.5);
+    const T tv1 = T(2) * v + T(1);
+    const T x2 = T(2) * x;
+    const T inv2x1 = T(1) / (x2 + T(1));
+    const T us = (v < T(2)) ? T(0.5) : T(0.5) / v;
+    const T ius = (v < T(2)) ? T(2) : T(2) * v;
+    const T lus = log(us);
+    const T den_h = fma(x2, us, T(1));
+    const T inv2xus1 = T(1) / den_h;
+    const LB_CONST_AS T *node = opaque_const<T>(&quad_nodes<T>()[0][0]);
+    const LB_CONST_AS T *wt = opaque_const<T>(gregory_tail<T>());
+    T G = T(0), H = T(0);
+    for (int j = 0; j < N; ++j) {
+        const T u = node[3 * j], lu = node[3 * j + 1], iu = node[3 * j + 2];
+        const T ub = exp(beta * lu);
+        const T lg = (T(1) - ub) + vm * log((x2 + ub) * inv2x1) + T(7) * lu;
+        const T lh = (ius - iu) - tv1 * (lu - lus) + vm * log(fma(x2, u, T(1)) * inv2xus1);
+        const T w = (j >= N - NT) ? wt[j - (N - NT)] : T(1);
+        G = fma(w, exp(lg), G);
+        H = fma(w, exp(lh), H);
+    }
+    const T mg = log(beta) - T(1) + vm * log(x2 + T(1));
+    const T mh = -ius - tv1 * lus + vm * log(den_h);
+    const T m = fmax(mg, mh);
+    const T li = -Cst<T>::log_n + m + log(G * exp(mg - m) + H * exp(mh - m));
+    return Cst<T>::half_log_pi - lgamma(v + T(0.5)) - v * log(x2) - x + li;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+
+// Value of the given branch.  binary32 evaluates the asymptotic branches in
+// binary32 and the fallback in binary64.
+template <typename T, int KIND>
+__device__ __forceinline__ T eval_branch(int b, T v, T x) {
+    if (b == BR_MU)
+        return br_mu20<T, KIND>(v, x);
+    if (b == BR_U)
+        return br_u13<T, KIND>(v, x);
+    if (KIND == KIND_I)
+        return T(br_series_i<double>(double(v), double(x)));
+    return T(br_quad_k<double>(double(v), double(x)));
+}
+
+// Full scalar evaluation (special values, branch choice, branch).
+template <typename T, int KIND>
+__device__ __forceinline__ T eval_scalar(T v, T x) {
+    if (KIND == KIND_K)
+        v = fabs(v);
+    T y;
+    if (special_value<T, KIND>(v, x, &y))
+        return y;
+    return eval_branch<T, KIND>(classify<T, KIND>(v, x), v, x);
+}
+
+}  // namespace lbessel

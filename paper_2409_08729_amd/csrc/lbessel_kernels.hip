@@ -1,0 +1,525 @@
+// HIP kernels and C-ABI entry points of liblbessel (gfx950, wave64).
+//
+// Grouped kernel (every public forward / derivative / vMF call):
+//   one workgroup = 256 threads = 4 wavefronts owns a tile of consecutive
+//   elements (2048 for one evaluation per element, 1024 for two).
+//   1. coalesced loads of (v, x); special values are resolved at once; every
+//      other evaluation gets its branch from its own (v, x);
+//   2. per branch, wavefront ballots + popcounts give per-wave counts and one
+//      short scan turns them into offsets of a branch-sorted list in LDS
+//      (fallback first, then Debye, then Hankel: most expensive first);
+//   3. the list is cut into 64-entry chunks that the wavefronts take from an
+//      LDS counter: each wavefront runs one branch on a full wave except for
+//      at most two boundary chunks per tile, and expensive chunks spread over
+//      the four wavefronts;
+//   4. results go straight to HBM (one evaluation per element) or to LDS and
+//      are combined per element (two orders per element for derivatives).
+// The branch of an evaluation depends only on its own (v, x), never on its
+// neighbours, so the grouped and the ungrouped kernel give the same bits.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbessel.h"
+#include "lbessel_device.hpp"
+
+namespace lbessel {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// Operation applied around the log-Bessel evaluation(s) of one element.
+enum : int {
+    OP_LOG = 0,       // out = log B_v(x)
+    OP_GRAD = 1,      // out = g * d/dx log B_v(x) from orders v and v + 1
+    OP_VMF = 2,       // out = (p/2-1) log k - (p/2) log 2pi - log I_{p/2-1}(k)
+    OP_VMF_GRAD = 3,  // out = -exp(log I_{p/2}(k) - log I_{p/2-1}(k))
+};
+
+template <int OP> struct OpTraits {
+    static constexpr int nv = (OP == OP_GRAD || OP == OP_VMF_GRAD) ? 2 : 1;
+    static constexpr bool scalar_order = (OP == OP_VMF || OP == OP_VMF_GRAD);
+};
+
+// Kernel arguments.  For the vMF operations v is unused, the order is the
+// scalar vs = p/2 - 1 and x holds kappa.
+template <typename T> struct Args {
+    const T *v;
+    const T *x;
+    const T *g;     // upstream gradient (OP_GRAD) or nullptr
+    T *out;
+    int64_t n;
+    T vs;           // scalar order (vMF)
+    T p;            // vMF dimension
+};
+
+template <typename T, int KIND, int OP>
+__device__ __forceinline__ T order_of(const Args<T> &a, int64_t i) {
+    if (OpTraits<OP>::scalar_order)
+        return a.vs;
+    const T v = a.v[i];
+    return (KIND == KIND_K) ? fabs(v) : v;
+}
+
+// Elements whose final result is a limit that needs no evaluation.
+template <typename T, int KIND, int OP>
+__device__ __forceinline__ bool element_special(T v, T x, T g, T p, T *res) {
+    const T inf = __builtin_huge_val();
+    const T nan = __builtin_nan("");
+    if (OP == OP_LOG) {
+        return special_value<T, KIND>(v, x, res);
+    } else if (OP == OP_GRAD) {
+        if (KIND == KIND_I) {
+            if (!(v >= T(0)) || !(x >= T(0)) || v == inf) { *res = nan; return true; }
+            if (x == T(0)) { *res = g * ((v == T(0)) ? T(0) : inf); return true; }
+            if (x == inf) { *res = g; return true; }
+        } else {
+            if (!(x >= T(0)) || v != v || v == inf) { *res = nan; return true; }
+            if (x == T(0)) { *res = -g * inf; return true; }
+            if (x == inf) { *res = -g; return true; }
+        }
+        return false;
+    } else if (OP == OP_VMF) {
+        if (!(x >= T(0)) || x == inf) { *res = nan; return true; }
+        if (x == T(0)) {
+            *res = v * Cst<T>::ln2 + lgamma(v + T(1)) - T(0.5) * p * Cst<T>::log_2pi;
+            return true;
+        }
+        return false;
+    } else {  // OP_VMF_GRAD
+        if (!(x >= T(0)) || x == inf) { *res = nan; return true; }
+        if (x == T(0)) { *res = T(0); return true; }
+        return false;
+    }
+}
+
+template <typename T, int KIND, int OP>
+__device__ __forceinline__ T combine(T v, T x, T g, T p, T y0, T y1) {
+    if (OP == OP_LOG)
+        return y0;
+    if (OP == OP_GRAD)
+        return (KIND == KIND_I) ? g * (exp(y1 - y0) + v / x) : g * (v / x - exp(y1 - y0));
+    if (OP == OP_VMF)
+        return v * log(x) - T(0.5) * p * Cst<T>::log_2pi - y0;
+    return -exp(y1 - y0);  // OP_VMF_GRAD
+}
+
+// One evaluation that may still hit a special value (the v + 1 order).
+template <typename T, int KIND>
+__device__ __forceinline__ T eval_full(T v, T x) {
+    T y;
+    if (special_value<T, KIND>(v, x, &y))
+        return y;
+    return eval_branch<T, KIND>(classify<T, KIND>(v, x), v, x);
+}
+
+// ---------------------------------------------------------------------------
+// Ungrouped kernel: one element per thread, no regrouping.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, int OP>
+__global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= a.n)
+        return;
+    const T v = order_of<T, KIND, OP>(a, i);
+    const T x = a.x[i];
+    const T g = (a.g != nullptr) ? a.g[i] : T(1);
+    T res;
+    if (element_special<T, KIND, OP>(v, x, g, a.p, &res)) {
+        a.out[i] = res;
+        return;
+    }
+    const T y0 = eval_full<T, KIND>(v, x);
+    const T y1 = (OpTraits<OP>::nv == 2) ? eval_full<T, KIND>(v + T(1), x) : y0;
+    a.out[i] = combine<T, KIND, OP>(v, x, g, a.p, y0, y1);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped kernel
+// ---------------------------------------------------------------------------
+template <int NV> struct TileCfg {
+    static constexpr int ept = (NV == 1) ? 8 : 4;        // elements per thread
+    static constexpr int tile = kThreads * ept;          // elements per tile
+    static constexpr int slots = ept * NV;               // evaluations per thread
+};
+
+template <typename T, int NV> struct Smem {
+    uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, branch-sorted
+    int cnt[3][TileCfg<NV>::slots][kWaves];              // counts, then offsets
+    int total[3];
+    int chunk;                                           // next chunk to evaluate
+    T res[(NV == 2) ? TileCfg<NV>::tile * 2 : 1];        // log-values of both orders
+};
+
+__device__ __forceinline__ int rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+}
+
+template <typename T, int KIND, int OP>
+__global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
+    constexpr int NV = OpTraits<OP>::nv;
+    constexpr int EPT = TileCfg<NV>::ept;
+    constexpr int TILE = TileCfg<NV>::tile;
+    constexpr int SLOTS = TileCfg<NV>::slots;
+    __shared__ Smem<T, NV> sm;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int64_t base = int64_t(blockIdx.x) * TILE;
+
+    // 1. load, screen, classify.  code: 2 bits per evaluation slot
+    //    (slot = r * NV + sub), BR_NONE = nothing to evaluate.
+    uint32_t code = 0;
+    uint32_t done = 0;   // bit r: element r finished in this step (or out of range)
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+        const int e = r * kThreads + tid;
+        const int64_t i = base + e;
+        int b0 = BR_NONE, b1 = BR_NONE;
+        if (i >= a.n) {
+            done |= 1u << r;
+        } else {
+            const T v = order_of<T, KIND, OP>(a, i);
+            const T x = a.x[i];
+            T res;
+            const T g = (a.g != nullptr) ? a.g[i] : T(1);
+            if (element_special<T, KIND, OP>(v, x, g, a.p, &res)) {
+                a.out[i] = res;
+                done |= 1u << r;
+            } else if (NV == 1) {
+                b0 = classify<T, KIND>(v, x);
+            } else {
+                T ys;
+                if (special_value<T, KIND>(v, x, &ys))
+                    sm.res[e * 2] = ys;
+                else
+                    b0 = classify<T, KIND>(v, x);
+                const T v1 = v + T(1);
+                if (special_value<T, KIND>(v1, x, &ys))
+                    sm.res[e * 2 + 1] = ys;
+                else
+                    b1 = classify<T, KIND>(v1, x);
+            }
+        }
+        code |= uint32_t(b0) << (2 * (r * NV));
+        if (NV == 2)
+            code |= uint32_t(b1) << (2 * (r * NV + 1));
+    }
+
+    // 2. per-wave counts per (branch, slot), then offsets
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int b = (code >> (2 * s)) & 3;
+#pragma unroll
+        for (int br = 0; br < 3; ++br) {
+            const uint64_t m = __ballot(b == br);
+            if (lane == 0)
+                sm.cnt[br][s][wave] = __popcll(m);
+        }
+    }
+    __syncthreads();
+    if (tid < 3) {
+        const int br = tid;
+        int run = 0;
+        for (int s = 0; s < SLOTS; ++s)
+            for (int w = 0; w < kWaves; ++w) {
+                const int c = sm.cnt[br][s][w];
+                sm.cnt[br][s][w] = run;
+                run += c;
+            }
+        sm.total[br] = run;
+    }
+    if (tid == 0)
+        sm.chunk = 0;
+    __syncthreads();
+    const int n_fb = sm.total[BR_FB];
+    const int n_u = sm.total[BR_U];
+    const int n_all = n_fb + n_u + sm.total[BR_MU];
+
+    // 3. scatter evaluation ids: [fallback | Debye | Hankel]
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int b = (code >> (2 * s)) & 3;
+#pragma unroll
+        for (int br = 0; br < 3; ++br) {
+            const uint64_t m = __ballot(b == br);
+            if (b == br) {
+                const int start = (br == BR_FB) ? 0 : (br == BR_U ? n_fb : n_fb + n_u);
+                const int pos = start + sm.cnt[br][s][wave] + rank_below(m);
+                const int r = s / NV, sub = s - (s / NV) * NV;
+                sm.list[pos] = uint16_t((r * kThreads + tid) * NV + sub);
+            }
+        }
+    }
+    __syncthreads();
+
+    // 4. evaluate 64-entry chunks
+    const int n_chunks = (n_all + 63) >> 6;
+    for (;;) {
+        int c = 0;
+        if (lane == 0)
+            c = atomicAdd(&sm.chunk, 1);
+        c = __shfl(c, 0);
+        if (c >= n_chunks)
+            break;
+        const int j = (c << 6) + lane;
+        if (j < n_all) {
+            const int id = sm.list[j];
+            const int e = id / NV;
+            const int sub = id - e * NV;
+            const int64_t i = base + e;
+            const int b = (j < n_fb) ? BR_FB : (j < n_fb + n_u ? BR_U : BR_MU);
+            const T v = order_of<T, KIND, OP>(a, i);
+            const T x = a.x[i];
+            const T y = eval_branch<T, KIND>(b, v + T(sub), x);
+            if (NV == 2) {
+                sm.res[id] = y;
+            } else {
+                const T g = (a.g != nullptr) ? a.g[i] : T(1);
+                a.out[i] = combine<T, KIND, OP>(v, x, g, a.p, y, y);
+            }
+        }
+    }
+
+    // 5. two-order operations: combine per element
+    if (NV == 2) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            if (done & (1u << r))
+                continue;
+            const int e = r * kThreads + tid;
+            const int64_t i = base + e;
+            const T v = order_of<T, KIND, OP>(a, i);
+            const T x = a.x[i];
+            const T g = (a.g != nullptr) ? a.g[i] : T(1);
+            a.out[i] = combine<T, KIND, OP>(v, x, g, a.p, sm.res[e * 2], sm.res[e * 2 + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics kernels
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, uint8_t *br,
+                                                       int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const T vv = (KIND == KIND_K) ? fabs(v[i]) : v[i];
+    T y;
+    br[i] = special_value<T, KIND>(vv, x[i], &y) ? uint8_t(BR_NONE)
+                                                 : uint8_t(classify<T, KIND>(vv, x[i]));
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_branch(int b, const double *v, const double *x,
+                                                     double *out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const double vv = (KIND == KIND_K) ? fabs(v[i]) : v[i];
+    double y;
+    if (!special_value<double, KIND>(vv, x[i], &y))
+        y = eval_branch<double, KIND>(b, vv, x[i]);
+    out[i] = y;
+}
+
+}  // namespace lbessel
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+using namespace lbessel;
+
+namespace {
+
+inline int launch_status() {
+    return (hipGetLastError() == hipSuccess) ? LBESSEL_OK : LBESSEL_EHIP;
+}
+
+inline bool grid_ok(int64_t n, int per_block, uint32_t *blocks) {
+    const int64_t b = (n + per_block - 1) / per_block;
+    if (b > int64_t(0x7fffffff))
+        return false;
+    *blocks = uint32_t(b);
+    return true;
+}
+
+template <typename T, int KIND, int OP>
+int run_grouped(const T *v, const T *x, const T *g, T *out, int64_t n, T vs, T p, void *s) {
+    if (n < 0)
+        return LBESSEL_EINVAL;
+    if (x == nullptr || out == nullptr || (!OpTraits<OP>::scalar_order && v == nullptr) ||
+        (OP == OP_GRAD && g == nullptr)) {
+        if (n > 0)
+            return LBESSEL_EINVAL;
+    }
+    if (n == 0)
+        return LBESSEL_OK;
+    uint32_t blocks;
+    if (!grid_ok(n, TileCfg<OpTraits<OP>::nv>::tile, &blocks))
+        return LBESSEL_EINVAL;
+    Args<T> a{v, x, g, out, n, vs, p};
+    hipLaunchKernelGGL((k_grouped<T, KIND, OP>), dim3(blocks), dim3(kThreads), 0,
+                       static_cast<hipStream_t>(s), a);
+    return launch_status();
+}
+
+template <typename T, int KIND>
+int run_ungrouped(const T *v, const T *x, T *out, int64_t n, void *s) {
+    if (n < 0 || (n > 0 && (v == nullptr || x == nullptr || out == nullptr)))
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    uint32_t blocks;
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    Args<T> a{v, x, nullptr, out, n, T(0), T(0)};
+    hipLaunchKernelGGL((k_ungrouped<T, KIND, OP_LOG>), dim3(blocks), dim3(kThreads), 0,
+                       static_cast<hipStream_t>(s), a);
+    return launch_status();
+}
+
+template <typename T>
+bool valid_dim(T p) {
+    return p == p && p >= T(2) && p < T(__builtin_huge_val());
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbessel_log_iv_f64(const double *v, const double *x, double *out, int64_t n, void *s) {
+    return run_grouped<double, KIND_I, OP_LOG>(v, x, nullptr, out, n, 0.0, 0.0, s);
+}
+int lbessel_log_iv_f32(const float *v, const float *x, float *out, int64_t n, void *s) {
+    return run_grouped<float, KIND_I, OP_LOG>(v, x, nullptr, out, n, 0.f, 0.f, s);
+}
+int lbessel_log_kv_f64(const double *v, const double *x, double *out, int64_t n, void *s) {
+    return run_grouped<double, KIND_K, OP_LOG>(v, x, nullptr, out, n, 0.0, 0.0, s);
+}
+int lbessel_log_kv_f32(const float *v, const float *x, float *out, int64_t n, void *s) {
+    return run_grouped<float, KIND_K, OP_LOG>(v, x, nullptr, out, n, 0.f, 0.f, s);
+}
+
+int lbessel_log_iv_grad_x_f64(const double *v, const double *x, const double *g, double *gx,
+                              int64_t n, void *s) {
+    return run_grouped<double, KIND_I, OP_GRAD>(v, x, g, gx, n, 0.0, 0.0, s);
+}
+int lbessel_log_iv_grad_x_f32(const float *v, const float *x, const float *g, float *gx,
+                              int64_t n, void *s) {
+    return run_grouped<float, KIND_I, OP_GRAD>(v, x, g, gx, n, 0.f, 0.f, s);
+}
+int lbessel_log_kv_grad_x_f64(const double *v, const double *x, const double *g, double *gx,
+                              int64_t n, void *s) {
+    return run_grouped<double, KIND_K, OP_GRAD>(v, x, g, gx, n, 0.0, 0.0, s);
+}
+int lbessel_log_kv_grad_x_f32(const float *v, const float *x, const float *g, float *gx,
+                              int64_t n, void *s) {
+    return run_grouped<float, KIND_K, OP_GRAD>(v, x, g, gx, n, 0.f, 0.f, s);
+}
+
+int lbessel_vmf_log_norm_f64(const double *kappa, double p, double *out, int64_t n, void *s) {
+    if (!valid_dim(p))
+        return LBESSEL_EINVAL;
+    return run_grouped<double, KIND_I, OP_VMF>(nullptr, kappa, nullptr, out, n, 0.5 * p - 1.0, p,
+                                               s);
+}
+int lbessel_vmf_log_norm_f32(const float *kappa, float p, float *out, int64_t n, void *s) {
+    if (!valid_dim(p))
+        return LBESSEL_EINVAL;
+    return run_grouped<float, KIND_I, OP_VMF>(nullptr, kappa, nullptr, out, n, 0.5f * p - 1.0f,
+                                              p, s);
+}
+int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out, int64_t n,
+                                  void *s) {
+    if (!valid_dim(p))
+        return LBESSEL_EINVAL;
+    return run_grouped<double, KIND_I, OP_VMF_GRAD>(nullptr, kappa, nullptr, out, n,
+                                                    0.5 * p - 1.0, p, s);
+}
+
+int lbessel_classify(int kind, int precision, const void *v, const void *x, uint8_t *branch,
+                     int64_t n, void *s) {
+    if (n < 0 || (kind != 0 && kind != 1) || (precision != 64 && precision != 32))
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (v == nullptr || x == nullptr || branch == nullptr)
+        return LBESSEL_EINVAL;
+    uint32_t blocks;
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(s);
+    if (precision == 64) {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_classify<double, KIND_I>), dim3(blocks), dim3(kThreads), 0, st,
+                               (const double *)v, (const double *)x, branch, n);
+        else
+            hipLaunchKernelGGL((k_classify<double, KIND_K>), dim3(blocks), dim3(kThreads), 0, st,
+                               (const double *)v, (const double *)x, branch, n);
+    } else {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_classify<float, KIND_I>), dim3(blocks), dim3(kThreads), 0, st,
+                               (const float *)v, (const float *)x, branch, n);
+        else
+            hipLaunchKernelGGL((k_classify<float, KIND_K>), dim3(blocks), dim3(kThreads), 0, st,
+                               (const float *)v, (const float *)x, branch, n);
+    }
+    return launch_status();
+}
+
+int lbessel_eval_branch_f64(int kind, int branch, const double *v, const double *x, double *out,
+                            int64_t n, void *s) {
+    if (n < 0 || (kind != 0 && kind != 1) || branch < 0 || branch > 2)
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (v == nullptr || x == nullptr || out == nullptr)
+        return LBESSEL_EINVAL;
+    uint32_t blocks;
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(s);
+    if (kind == 0)
+        hipLaunchKernelGGL(k_branch<KIND_I>, dim3(blocks), dim3(kThreads), 0, st, branch, v, x,
+                           out, n);
+    else
+        hipLaunchKernelGGL(k_branch<KIND_K>, dim3(blocks), dim3(kThreads), 0, st, branch, v, x,
+                           out, n);
+    return launch_status();
+}
+
+int lbessel_eval_ungrouped(int kind, int precision, const void *v, const void *x, void *out,
+                           int64_t n, void *s) {
+    if ((kind != 0 && kind != 1) || (precision != 64 && precision != 32))
+        return LBESSEL_EINVAL;
+    if (precision == 64) {
+        if (kind == 0)
+            return run_ungrouped<double, KIND_I>((const double *)v, (const double *)x,
+                                                 (double *)out, n, s);
+        return run_ungrouped<double, KIND_K>((const double *)v, (const double *)x, (double *)out,
+                                             n, s);
+    }
+    if (kind == 0)
+        return run_ungrouped<float, KIND_I>((const float *)v, (const float *)x, (float *)out, n,
+                                            s);
+    return run_ungrouped<float, KIND_K>((const float *)v, (const float *)x, (float *)out, n, s);
+}
+
+int lbessel_abi_version(void) { return LBESSEL_ABI_VERSION; }
+
+const char *lbessel_status_string(int status) {
+    switch (status) {
+    case LBESSEL_OK: return "ok";
+    case LBESSEL_EINVAL: return "invalid argument";
+    case LBESSEL_EHIP: return "HIP launch failure";
+    case LBESSEL_ENODEV: return "no usable device";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

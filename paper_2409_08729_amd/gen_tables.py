@@ -1,0 +1,248 @@
+"""Build-time generator of the constant tables the HIP kernels use.
+
+Everything is derived in exact rational arithmetic and rounded once, to
+nearest, into binary64 and binary32 hex literals:
+
+* Debye polynomials u_k(t), k = 1..13, from u_0 = 1 and
+  u_{k+1}(t) = 1/2 t^2 (1 - t^2) u_k'(t) + 1/8 int_0^t (1 - 5 s^2) u_k(s) ds
+  (paper, Sec. "Modified Bessel function of the first kind", eqs. (u0), (uk);
+  DLMF 10.41.10).  u_k(t) = t^k P_k(t^2) with P_k of degree k, so the kernels
+  evaluate sum_k (t/v)^k P_k(t^2) by Horner in t^2 inside and in t/v outside.
+* Node weights of the composite rule on u_j = j/N, N = 600, for the integral of
+  log K_v (paper, eq. (log Kv integral) and the composite rule that follows it):
+  the trapezoid rule with a Gregory end correction of order 8 at u = 1.  No
+  correction is needed at u = 0, where both integrands vanish to high order
+  (g ~ u^7, h ~ exp(-1/u)).  The paper's Simpson weights are emitted as well.
+* Per-node constants log u_j and 1/u_j.
+
+Run as a script it writes ``csrc/lbessel_tables.h``.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+U_TERMS = 13         # Debye terms on the asymptotic branch (U_13)
+MU_TERMS = 20        # Hankel correction terms (mu_20)
+QUAD_N = 600         # nodes of the composite rule (paper: N = 600)
+GREGORY_ORDER = 8    # backward differences used by the end correction
+
+
+# ----------------------------------------------------------------------------
+# Debye polynomials
+# ----------------------------------------------------------------------------
+
+def debye_polys(kmax: int = U_TERMS + 1) -> list[dict[int, Fraction]]:
+    """u_0..u_kmax as {power of t: coefficient}."""
+    polys = [{0: Fraction(1)}]
+    for _ in range(kmax):
+        u = polys[-1]
+        nxt: dict[int, Fraction] = {}
+        # 1/2 (t^2 - t^4) u'(t)
+        for p, c in u.items():
+            if p == 0:
+                continue
+            d = c * p                                    # coefficient of t^{p-1}
+            nxt[p + 1] = nxt.get(p + 1, Fraction(0)) + d / 2
+            nxt[p + 3] = nxt.get(p + 3, Fraction(0)) - d / 2
+        # 1/8 int_0^t (1 - 5 s^2) u(s) ds
+        for p, c in u.items():
+            nxt[p + 1] = nxt.get(p + 1, Fraction(0)) + c / (8 * (p + 1))
+            nxt[p + 3] = nxt.get(p + 3, Fraction(0)) - 5 * c / (8 * (p + 3))
+        polys.append({p: c for p, c in nxt.items() if c != 0})
+    return polys
+
+
+def debye_p_coeffs(k: int, polys=None) -> list[Fraction]:
+    """Coefficients c_0..c_k of P_k with u_k(t) = t^k sum_j c_j t^{2j}."""
+    polys = polys or debye_polys(k)
+    u = polys[k]
+    out = []
+    for j in range(k + 1):
+        out.append(u.get(k + 2 * j, Fraction(0)))
+    assert set(u) <= {k + 2 * j for j in range(k + 1)}
+    return out
+
+
+# ----------------------------------------------------------------------------
+# quadrature weights
+# ----------------------------------------------------------------------------
+
+def gregory_coefficients(m: int) -> list[Fraction]:
+    """Coefficients c_0..c_m of z / log(1+z) = sum c_j z^j (c_1 = 1/2, c_2 = -1/12, ...).
+
+    The Gregory end correction for the trapezoid rule at the right end is
+    -h sum_{k>=1} |c_{k+1}| nabla^k f_N.
+    """
+    # log(1+z)/z = sum_j (-1)^j z^j / (j+1); invert the power series.
+    a = [Fraction((-1) ** j, j + 1) for j in range(m + 1)]
+    c = [Fraction(0)] * (m + 1)
+    c[0] = 1 / a[0]
+    for j in range(1, m + 1):
+        c[j] = -sum(a[i] * c[j - i] for i in range(1, j + 1)) / a[0]
+    return c
+
+
+def trapezoid_gregory_weights(n: int = QUAD_N, order: int = GREGORY_ORDER) -> list[Fraction]:
+    """Weights w_0..w_n (in units of h = 1/n) of the trapezoid rule on [0, 1] with
+    the right-end Gregory correction using nabla^1..nabla^order at u = 1."""
+    w = [Fraction(1)] * (n + 1)
+    w[0] = Fraction(1, 2)
+    w[n] = Fraction(1, 2)
+    c = gregory_coefficients(order + 1)
+    for k in range(1, order + 1):
+        gk = abs(c[k + 1])
+        # nabla^k f_n = sum_m (-1)^m C(k, m) f_{n-m}
+        for m in range(k + 1):
+            w[n - m] -= gk * (-1) ** m * math.comb(k, m)
+    return w
+
+
+def simpson_weights(n: int = QUAD_N) -> list[Fraction]:
+    """Composite Simpson 1/3 weights in units of h = 1/n: (1, 4, 2, 4, ..., 4, 1)/3."""
+    assert n % 2 == 0
+    w = [Fraction(2, 3) if j % 2 == 0 else Fraction(4, 3) for j in range(n + 1)]
+    w[0] = w[n] = Fraction(1, 3)
+    return w
+
+
+# ----------------------------------------------------------------------------
+# rounding and emission
+# ----------------------------------------------------------------------------
+
+def to_f64(q: Fraction) -> float:
+    return q.numerator / q.denominator          # correctly rounded in CPython
+
+
+def to_f32_exact(q: Fraction) -> float:
+    """Round a rational to the nearest binary32 (ties to even), returned as a float."""
+    if q == 0:
+        return 0.0
+    sign = -1 if q < 0 else 1
+    a = abs(q)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)                              # subnormal range
+    scale = Fraction(2) ** (23 - e)
+    m = a * scale                                 # in [2^23, 2^24) for normals
+    mi = m.numerator // m.denominator
+    rem = m - mi
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and mi % 2 == 1):
+        mi += 1
+    return sign * float(Fraction(mi) / scale)
+
+
+def node_constants(n: int = QUAD_N):
+    """(u_j, log u_j, 1/u_j) for j = 1..n as exact rationals / 50-digit decimals."""
+    from decimal import Decimal, localcontext
+    out = []
+    with localcontext() as ctx:
+        ctx.prec = 50
+        for j in range(1, n + 1):
+            u = Fraction(j, n)
+            lu = (Decimal(j) / Decimal(n)).ln()
+            out.append((u, lu, 1 / u))
+    return out
+
+
+def dec_to_f64(d) -> float:
+    """Nearest binary64 to a Decimal (via its exact rational value)."""
+    return to_f64(Fraction(d))
+
+
+def dec_to_f32(d) -> float:
+    return to_f32_exact(Fraction(d))
+
+
+def f64_hex(x: float) -> str:
+    return float(x).hex()
+
+
+def f32_hex(x: float) -> str:
+    return float(x).hex() + "f"
+
+
+def _debye_arrays():
+    polys = debye_polys(U_TERMS)
+    rows = [debye_p_coeffs(k, polys) for k in range(1, U_TERMS + 1)]
+    return rows
+
+
+def render_header() -> str:
+    rows = _debye_arrays()
+    lines = [
+        "// Generated by paper_2409_08729_amd/gen_tables.py: do not edit.",
+        "// Exact rationals rounded once to nearest.",
+        "#pragma once",
+        "",
+        "namespace lbessel {",
+        "namespace tables {",
+        "",
+        f"constexpr int kUTerms = {U_TERMS};",
+        f"constexpr int kMuTerms = {MU_TERMS};",
+        f"constexpr int kQuadN = {QUAD_N};",
+        f"constexpr int kGregoryOrder = {GREGORY_ORDER};",
+        "",
+        "// P_k(p), u_k(t) = t^k P_k(t^2); row k-1 holds c_0..c_k (unused tail = 0).",
+    ]
+    for name, conv, fmt, ty in (("kDebyeP64", to_f64, f64_hex, "double"),
+                                ("kDebyeP32", to_f32_exact, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[{U_TERMS}][{U_TERMS + 1}] = {{")
+        for k, row in enumerate(rows, start=1):
+            vals = [fmt(conv(c)) for c in row] + ["0"] * (U_TERMS - k)
+            lines.append("    {" + ", ".join(vals) + "},")
+        lines.append("};")
+    # Hankel expansion: c_k = c_{k-1} (mu - (2k-1)^2) / k * s/(8x), k = 1..20,
+    # evaluated as fma(mu, 1/k, -(2k-1)^2/k): rows {1/k, (2k-1)^2/k}.
+    lines.append("")
+    lines.append("// Hankel recurrence constants, row k-1 = {1/k, (2k-1)^2/k}, k = 1..20.")
+    for name, conv, fmt, ty in (("kHankel64", to_f64, f64_hex, "double"),
+                                ("kHankel32", to_f32_exact, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[{MU_TERMS}][2] = {{")
+        for k in range(1, MU_TERMS + 1):
+            lines.append("    {" + fmt(conv(Fraction(1, k))) + ", "
+                         + fmt(conv(Fraction((2 * k - 1) ** 2, k))) + "},")
+        lines.append("};")
+    # quadrature: right-end weights that differ from 1 (trapezoid + Gregory)
+    w = trapezoid_gregory_weights()
+    tail = [w[j] for j in range(QUAD_N - GREGORY_ORDER, QUAD_N + 1)]
+    lines.append("")
+    lines.append("// Weights of nodes N-order..N (h = 1/N units); all interior weights are 1.")
+    for name, conv, fmt, ty in (("kGregoryTail64", to_f64, f64_hex, "double"),
+                                ("kGregoryTail32", to_f32_exact, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[{GREGORY_ORDER + 1}] = {{"
+                     + ", ".join(fmt(conv(t)) for t in tail) + "};")
+    # per-node constants, j = 1..N (index j-1)
+    nodes = node_constants()
+    lines.append("")
+    lines.append("// Node constants for u_j = j/N, j = 1..N (row j-1): {u_j, log u_j, 1/u_j}.")
+    for name, conv_q, conv_d, fmt, ty in (
+            ("kQuadNode64", to_f64, dec_to_f64, f64_hex, "double"),
+            ("kQuadNode32", to_f32_exact, dec_to_f32, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[{QUAD_N}][3] = {{")
+        for u, lu, iu in nodes:
+            lines.append("    {" + ", ".join((fmt(conv_q(u)), fmt(conv_d(lu)), fmt(conv_q(iu))))
+                         + "},")
+        lines.append("};")
+    lines.append("")
+    lines.append("}  // namespace tables")
+    lines.append("}  // namespace lbessel")
+    lines.append("")
+    return "\n".join(lines)
+
+
+def write_header(path: str | None = None) -> str:
+    path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc",
+                                "lbessel_tables.h")
+    text = render_header()
+    old = open(path).read() if os.path.exists(path) else None
+    if old != text:
+        with open(path, "w") as f:
+            f.write(text)
+    return path
+
+
+if __name__ == "__main__":
+    print(write_header())

@@ -1,0 +1,70 @@
+"""Seeded synthetic inputs (no arithmetic of the method lives here).
+
+Shapes follow the paper's experiments (arXiv 2409.08729):
+  * per-order sets: v fixed to 2^k, k = 0..10, x uniform in [1, 100) (the
+    runtime comparison of the introduction, 20M values of x per order);
+  * a stress grid with v log-uniform in [1e-3, 1e4] and x log-uniform in
+    [1e-4, 1e4], covering the under/overflow regions of naive evaluation;
+  * the Small [0, 150]^2 and Large [150, 1e4]^2 ([150, 4000]^2 for K) test
+    regions (Sec. "Test Regions"), and the v ~ 100, x ~ 0.1 corner the paper
+    re-checked by hand (Sec. "Precision").
+All generators use numpy's PCG64 (default_rng) with a fixed seed, so every
+array is reproducible bit for bit on any host.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_M1 = 20240913
+SEED_M2 = 20240914
+SEED_M3 = 20240915
+ORDERS = tuple(float(2 ** k) for k in range(11))
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def m1(n: int = 65536, seed: int = SEED_M1):
+    """v uniform on {2^0..2^10}, x uniform in [1, 100) (float64)."""
+    g = rng(seed)
+    v = np.ldexp(1.0, g.integers(0, 11, n)).astype(np.float64)
+    x = g.uniform(1.0, 100.0, n)
+    return v, x
+
+
+def m2_order(k: int, n: int = 20_000_000, seed: int = SEED_M2):
+    """One order of the per-order set: v = 2^k for all n, x uniform in [1, 100)."""
+    g = rng(seed + 1000 * k)
+    x = g.uniform(1.0, 100.0, n)
+    v = np.full(n, float(2 ** k))
+    return v, x
+
+
+def m3(n: int = 1 << 26, seed: int = SEED_M3):
+    """Stress grid: log10 v ~ U[-3, 4], log10 x ~ U[-4, 4], independent."""
+    g = rng(seed)
+    v = 10.0 ** g.uniform(-3.0, 4.0, n)
+    x = 10.0 ** g.uniform(-4.0, 4.0, n)
+    return v, x
+
+
+def small_region(n: int, seed: int = 7):
+    g = rng(seed)
+    return g.uniform(0.0, 150.0, n), g.uniform(0.0, 150.0, n)
+
+
+def large_region(n: int, kind: str = "I", seed: int = 8):
+    g = rng(seed)
+    hi = 1e4 if kind == "I" else 4000.0
+    return g.uniform(150.0, hi, n), g.uniform(150.0, hi, n)
+
+
+def corner_v100_x01(n: int, seed: int = 9):
+    g = rng(seed)
+    return g.uniform(90.0, 110.0, n), g.uniform(0.05, 0.2, n)
+
+
+def band(n: int, vlo: float, vhi: float, xlo: float, xhi: float, seed: int = 10):
+    g = rng(seed)
+    return g.uniform(vlo, vhi, n), g.uniform(xlo, xhi, n)

@@ -1,0 +1,76 @@
+"""C-ABI surface, host only: the library loads, exports every symbol that
+include/lbessel.h declares, and rejects bad arguments before any GPU call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbessel.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbessel_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2409_08729_amd as lb
+    return lb.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_version_and_status(lib):
+    assert lib.lbessel_abi_version() == 1
+    assert lib.lbessel_status_string(0) == b"ok"
+    assert lib.lbessel_status_string(-1) == b"invalid argument"
+    assert lib.lbessel_status_string(-2) == b"HIP launch failure"
+    assert lib.lbessel_status_string(12345) == b"unknown status"
+
+
+@pytest.mark.parametrize("name", ["lbessel_log_iv_f64", "lbessel_log_iv_f32",
+                                  "lbessel_log_kv_f64", "lbessel_log_kv_f32"])
+def test_forward_argument_checks(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, None, 0, None) == 0          # n = 0: nothing to do
+    assert fn(None, None, None, -1, None) == -1        # n < 0
+    assert fn(None, None, None, 16, None) == -1        # NULL with n > 0
+
+
+@pytest.mark.parametrize("name", ["lbessel_log_iv_grad_x_f64", "lbessel_log_kv_grad_x_f64",
+                                  "lbessel_log_iv_grad_x_f32", "lbessel_log_kv_grad_x_f32"])
+def test_grad_argument_checks(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, None, None, 0, None) == 0
+    assert fn(None, None, None, None, 8, None) == -1
+
+
+def test_vmf_argument_checks(lib):
+    assert lib.lbessel_vmf_log_norm_f64(None, 1.5, None, 0, None) == -1   # p < 2
+    assert lib.lbessel_vmf_log_norm_f64(None, float("nan"), None, 0, None) == -1
+    assert lib.lbessel_vmf_log_norm_f64(None, 3.0, None, 0, None) == 0
+    assert lib.lbessel_vmf_log_norm_f64(None, 3.0, None, 5, None) == -1
+    assert lib.lbessel_vmf_log_norm_grad_f64(None, 1.0, None, 0, None) == -1
+
+
+def test_diagnostic_argument_checks(lib):
+    assert lib.lbessel_classify(2, 64, None, None, None, 0, None) == -1     # bad kind
+    assert lib.lbessel_classify(0, 16, None, None, None, 0, None) == -1     # bad precision
+    assert lib.lbessel_eval_branch_f64(0, 3, None, None, None, 0, None) == -1
+    assert lib.lbessel_eval_ungrouped(1, 64, None, None, None, 0, None) == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    import paper_2409_08729_amd as lb
+    with pytest.raises(lb.LbesselError):
+        lb.log_iv(torch.ones(4, dtype=torch.float64), torch.ones(4, dtype=torch.float64))

@@ -1,0 +1,101 @@
+"""Host checks of the generated constant tables (no GPU).
+
+* Debye polynomials: the printed u_1, u_2, u_3 (DLMF 10.41.10, A&S 9.3.9) and
+  u_k(1) = (-1)^k gamma_k for k <= 14, gamma_k the Stirling-series
+  coefficients of Gamma*(v) = Gamma(v+1) / (sqrt(2 pi v) (v/e)^v), derived here
+  independently from Bernoulli numbers (DLMF 5.11.1 / 5.11.10).
+* Quadrature weights: sum to N, integrate smooth functions that vanish at 0
+  to ~1e-17, and reproduce the v = 1/2 integral (exactly 1) in binary64.
+"""
+from fractions import Fraction
+import math
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, os.path.join(ROOT, "paper_2409_08729_amd"))
+import gen_tables as gt  # noqa: E402
+sys.path.pop(0)
+
+import closed_forms as cf  # noqa: E402
+
+
+def test_debye_low_orders_match_printed():
+    polys = gt.debye_polys(3)
+    assert polys[1] == {1: Fraction(3, 24), 3: Fraction(-5, 24)}
+    assert polys[2] == {2: Fraction(81, 1152), 4: Fraction(-462, 1152), 6: Fraction(385, 1152)}
+    assert polys[3] == {3: Fraction(30375, 414720), 5: Fraction(-369603, 414720),
+                        7: Fraction(765765, 414720), 9: Fraction(-425425, 414720)}
+
+
+def _stirling_gamma_coeffs(m):
+    """gamma_1..gamma_m of Gamma*(v) ~ sum gamma_k v^-k, from
+    log Gamma*(v) ~ sum_{j>=1} B_{2j} / (2j (2j-1) v^{2j-1})."""
+    # log series coefficients l_k of v^-k
+    lser = [Fraction(0)] * (m + 1)
+    for j in range(1, m // 2 + 2):
+        k = 2 * j - 1
+        if k <= m:
+            lser[k] = cf.bernoulli(2 * j) / (2 * j * (2 * j - 1))
+    # exp of a power series with zero constant term: e' = l' e
+    e = [Fraction(0)] * (m + 1)
+    e[0] = Fraction(1)
+    for n in range(1, m + 1):
+        e[n] = sum(k * lser[k] * e[n - k] for k in range(1, n + 1)) / n
+    return e
+
+
+def test_debye_at_t_equal_one_is_stirling():
+    m = 14
+    gam = _stirling_gamma_coeffs(m)
+    assert gam[1] == Fraction(1, 12) and gam[2] == Fraction(1, 288)
+    polys = gt.debye_polys(m)
+    for k in range(1, m + 1):
+        uk1 = sum(polys[k].values())
+        assert uk1 == (-1) ** k * gam[k], k
+
+
+def test_debye_parity_and_degree():
+    for k in range(1, 14):
+        c = gt.debye_p_coeffs(k)
+        assert len(c) == k + 1 and c[-1] != 0 and c[0] != 0
+
+
+def test_gregory_weights():
+    w = gt.trapezoid_gregory_weights()
+    n = gt.QUAD_N
+    assert sum(w) == n
+    assert all(wj == 1 for wj in w[1:n - gt.GREGORY_ORDER])
+    # functions flat at u = 0 (all derivatives < 9 vanish): integrate to ~h^10
+    for d in (9, 12, 16, 25):
+        approx = sum(w[j] * Fraction(j, n) ** d for j in range(n + 1)) / n
+        assert abs(approx - Fraction(1, d + 1)) < Fraction(1, 10 ** 17), d
+    # plain trapezoid would be off by ~d/(12 N^2)
+    d = 12
+    trap = (sum(Fraction(j, n) ** d for j in range(n + 1)) - Fraction(1, 2)) / n
+    assert abs(trap - Fraction(1, d + 1)) > Fraction(1, 10 ** 7)
+
+
+def test_half_order_integral_is_one_in_binary64():
+    """v = 1/2: int_0^1 (g + h) du = (1 - 1/e) + 1/e = 1 (the Simpson constant of the
+    paper printed as 1/(6N) would give 1/2 here)."""
+    nodes = gt.node_constants()
+    u = np.array([float(a) for a, _, _ in nodes])
+    w = np.array([float(x) for x in gt.trapezoid_gregory_weights()[1:]])
+    beta = 8.0
+    x = 3.0
+    g = beta * np.exp(-u ** beta) * (2 * x + u ** beta) ** 0.0 * u ** 7
+    h = np.exp(-1 / u) * u ** -2.0 * (2 * x * u + 1) ** 0.0
+    val = (w * (g + h)).sum() / gt.QUAD_N
+    assert abs(val - 1.0) < 4e-16
+    ws = np.array([float(x) for x in gt.simpson_weights()[1:]])
+    assert abs((ws * (g + h)).sum() / gt.QUAD_N - 1.0) < 1e-9
+
+
+def test_rounding_helpers():
+    assert gt.to_f32_exact(Fraction(1, 3)) == float(np.float32(1 / 3))
+    assert gt.to_f32_exact(Fraction(-5, 24)) == float(np.float32(-5 / 24))
+    lu = gt.node_constants(600)[0][1]
+    assert gt.dec_to_f64(lu) == math.log(1 / 600) or abs(gt.dec_to_f64(lu) - math.log(1 / 600)) <= 1e-15
