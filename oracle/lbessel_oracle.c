@@ -47,6 +47,11 @@
  *      x > 0) -> +inf; both infinite -> NaN.
  * Results are returned as (hi, lo) double pairs with hi + lo == the binary128
  * value rounded twice (hi = RN(q), lo = RN(q - hi)).
+ *
+ * Range: the series needs O(sqrt(x)) terms, so I is not computed (NaN) for
+ * x > 1e12; the trapezoid rule needs the log-integrand resolved to O(1) at
+ * its peak, so K is not computed (NaN) for x > 1e15 or |v| > 1e15, where the
+ * log-integrand exceeds 2^113 in size.  Tests use closed forms there.
  */
 #include <quadmath.h>
 #include <stdint.h>
@@ -58,6 +63,10 @@ typedef __float128 qf;
 
 #define Q_NAN (nanq(""))
 #define Q_INF (HUGE_VALQ)
+
+/* Largest arguments the oracle evaluates (see the header). */
+static const qf MAX_X_SERIES = 1e12Q;
+static const qf MAX_K_ARG = 1e15Q;
 
 /* Truncation target of the series tail, relative to the partial sum. */
 static const qf SERIES_TAIL = 3.00926553810505e-36Q; /* 2^-118 */
@@ -140,6 +149,8 @@ static qf log_iv_q(qf v, qf x)
         return v == 0 ? 0 : -Q_INF;
     if (isinfq(x))
         return Q_INF;
+    if (x > MAX_X_SERIES)
+        return Q_NAN;
     qf li;
     series_iv(v, x, &li, NULL);
     return li;
@@ -153,6 +164,8 @@ static qf dlog_iv_q(qf v, qf x)
         return v == 0 ? 0 : Q_INF;
     if (isinfq(x))
         return 1;
+    if (x > MAX_X_SERIES)
+        return Q_NAN;
     qf li, d;
     series_iv(v, x, &li, &d);
     return d;
@@ -219,7 +232,7 @@ static qf kwidth(const kint *p, qf tpk, qf fmax)
 {
     const qf target = fmax - 1;
     /* right side: kphi -> -inf, bracket by doubling */
-    qf a = 0, b = 1e-6Q;
+    qf a = 0, b = 1e-3Q / sqrtq(1 + p->x + p->v);
     while (kphi(p, tpk + b) >= target)
         b *= 2;
     for (int it = 0; it < 60; ++it) {
@@ -338,6 +351,8 @@ static qf log_kv_q(qf v, qf x)
         return Q_INF;
     if (isinfq(x))
         return -Q_INF;
+    if (x > MAX_K_ARG || v > MAX_K_ARG)
+        return Q_NAN;
     kint p = {v, x, 0};
     return klog_integral(&p);
 }
@@ -353,6 +368,8 @@ static qf dlog_kv_q(qf v, qf x)
         return -Q_INF;
     if (isinfq(x))
         return -1;
+    if (x > MAX_K_ARG || v > MAX_K_ARG)
+        return Q_NAN;
     kint p0 = {v, x, 0};
     kint p1 = {v, x, 1};
     return -expq(klog_integral(&p1) - klog_integral(&p0));

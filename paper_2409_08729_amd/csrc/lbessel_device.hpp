@@ -83,13 +83,16 @@ template <> struct Regime<double, KIND_I> {
 template <> struct Regime<double, KIND_K> {
     static constexpr RegimeSet r = {17.5, 8.5, 0x1.0388657115a47p+2, 17.5, 20.0, 0.1, 14.5};
 };
-// binary32 uses the binary64 regions (its fallback branch is evaluated in
-// binary64, the asymptotic ones in binary32).
+// binary32 sets (2e-6 target): the expansions reach further down in x, but
+// two binary32 rounding effects bound them: the Debye polynomials P_k(t^2)
+// cancel near t = 1 (coefficients up to ~1e12 against values ~1), which
+// needs v > 9 for all x; and the alternating Hankel sum for I amplifies
+// rounding by ~exp(v^2/x), which needs v^2 < 2x (and v < 4.5 on the box).
 template <> struct Regime<float, KIND_I> {
-    static constexpr RegimeSet r = Regime<double, KIND_I>::r;
+    static constexpr RegimeSet r = {9.5, 4.5, 2.0, 9.5, 7.5, 0.1, 9.0};
 };
 template <> struct Regime<float, KIND_K> {
-    static constexpr RegimeSet r = Regime<double, KIND_K>::r;
+    static constexpr RegimeSet r = {7.5, 16.0, 0x1.d8e64b8d4ddaep+2, 7.5, 7.0, 0.1, 9.0};
 };
 
 // ---------------------------------------------------------------------------
@@ -255,7 +258,8 @@ template <> __device__ __forceinline__ const float *gregory_tail<float>() {
     return tables::kGregoryTail32;
 }
 
-template <typename T>
+// ACC: type of the two 600-term sums (binary64 also for binary32 terms).
+template <typename T, typename ACC>
 __device__ __forceinline__ T br_quad_k(T v, T x) {
     constexpr int N = tables::kQuadN;
     constexpr int NT = tables::kGregoryOrder + 1;   // nodes with weight != 1
@@ -271,20 +275,20 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
     const T inv2xus1 = T(1) / den_h;
     const LB_CONST_AS T *node = opaque_const<T>(&quad_nodes<T>()[0][0]);
     const LB_CONST_AS T *wt = opaque_const<T>(gregory_tail<T>());
-    T G = T(0), H = T(0);
+    ACC G = ACC(0), H = ACC(0);
     for (int j = 0; j < N; ++j) {
         const T u = node[3 * j], lu = node[3 * j + 1], iu = node[3 * j + 2];
         const T ub = exp(beta * lu);
         const T lg = (T(1) - ub) + vm * log((x2 + ub) * inv2x1) + T(7) * lu;
         const T lh = (ius - iu) - tv1 * (lu - lus) + vm * log(fma(x2, u, T(1)) * inv2xus1);
         const T w = (j >= N - NT) ? wt[j - (N - NT)] : T(1);
-        G = fma(w, exp(lg), G);
-        H = fma(w, exp(lh), H);
+        G = fma(ACC(w), ACC(exp(lg)), G);
+        H = fma(ACC(w), ACC(exp(lh)), H);
     }
     const T mg = log(beta) - T(1) + vm * log(x2 + T(1));
     const T mh = -ius - tv1 * lus + vm * log(den_h);
     const T m = fmax(mg, mh);
-    const T li = -Cst<T>::log_n + m + log(G * exp(mg - m) + H * exp(mh - m));
+    const T li = -Cst<T>::log_n + m + log(T(G * ACC(exp(mg - m)) + H * ACC(exp(mh - m))));
     return Cst<T>::half_log_pi - lgamma(v + T(0.5)) - v * log(x2) - x + li;
 }
 
@@ -292,8 +296,8 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
 // Dispatch
 // ---------------------------------------------------------------------------
 
-// Value of the given branch.  binary32 evaluates the asymptotic branches in
-// binary32 and the fallback in binary64.
+// Value of the given branch.  binary32 computes everything in binary32
+// except the two 600-term sums of the integral, accumulated in binary64.
 template <typename T, int KIND>
 __device__ __forceinline__ T eval_branch(int b, T v, T x) {
     if (b == BR_MU)
@@ -301,8 +305,8 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x) {
     if (b == BR_U)
         return br_u13<T, KIND>(v, x);
     if (KIND == KIND_I)
-        return T(br_series_i<double>(double(v), double(x)));
-    return T(br_quad_k<double>(double(v), double(x)));
+        return br_series_i<T>(v, x);
+    return br_quad_k<T, double>(v, x);
 }
 
 // Full scalar evaluation (special values, branch choice, branch).

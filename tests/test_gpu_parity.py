@@ -124,8 +124,9 @@ def test_zero_crossings_and_special_orders(lb, oracle, kind):
 @pytest.mark.parametrize("kind", ["I", "K"])
 def test_special_values(lb, oracle, kind):
     inf, nan = np.inf, np.nan
-    vals = [0.0, -0.0, 1e-300, 0.3, 1.0, 2.5, 30.0, 1e300, inf, -1.0, -2.5, nan]
-    xs = [0.0, -0.0, 1e-300, 1e-4, 0.5, 19.9, 25.0, 1e4, 1e300, inf, -1.0, nan]
+    big_v = 1e300 if kind == "I" else 1e12        # the K oracle stops at |v| = 1e15
+    vals = [0.0, -0.0, 1e-300, 0.3, 1.0, 2.5, 30.0, 1e8, big_v, inf, -1.0, -2.5, nan]
+    xs = [0.0, -0.0, 1e-300, 1e-4, 0.5, 19.9, 25.0, 1e4, 1e6, inf, -1.0, nan]
     V, X = np.meshgrid(np.array(vals), np.array(xs), indexing="ij")
     v, x = V.ravel(), X.ravel()
     y = run(lb, kind, v, x)
@@ -140,6 +141,28 @@ def test_special_values(lb, oracle, kind):
     assert np.isfinite(y[m]).all(), (v[m][~np.isfinite(y[m])], x[m][~np.isfinite(y[m])])
     e = cond_err(y[m], hi[m], lo[m], v[m], x[m])
     assert e.max() <= TOL64, (v[m][np.argmax(e)], x[m][np.argmax(e)], e.max())
+
+
+def test_huge_arguments_match_leading_terms(lb):
+    """x up to 1e300 (beyond the oracle's range): with v^2 << x the Hankel
+    correction is below rounding, so log I = x - log(2 pi x)/2 and
+    log K = log(pi/(2x))/2 - x to the last bit of x; both stay finite."""
+    x = np.array([1e20, 1e50, 1e100, 1e200, 1e300, 1.7e308])
+    v = np.array([0.0, 0.3, 2.0, 1e3, 1e20, 1e50])
+    yi = run(lb, "I", v, x)
+    yk = run(lb, "K", v, x)
+    assert np.isfinite(yi).all() and np.isfinite(yk).all()
+    np.testing.assert_allclose(yi, x - 0.5 * np.log(2 * np.pi * x), rtol=4e-16)
+    np.testing.assert_allclose(yk, 0.5 * np.log(np.pi / (2 * x)) - x, rtol=4e-16)
+    # tiny x, huge v: log I -> v log(x/2) - lgamma(v+1), finite
+    v = np.array([1e4, 1e8, 1e12])
+    x = np.array([1e-300, 1e-100, 1e-10])
+    yi = run(lb, "I", v, x)
+    yk = run(lb, "K", v, x)
+    assert np.isfinite(yi).all() and np.isfinite(yk).all()
+    from math import lgamma
+    ref = np.array([vv * np.log(xx / 2) - lgamma(vv + 1) for vv, xx in zip(v, x)])
+    np.testing.assert_allclose(yi, ref, rtol=1e-13)
 
 
 # ---------------------------------------------------------------------------
