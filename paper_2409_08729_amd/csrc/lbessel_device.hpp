@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbessel_fastmath.hpp"
 #include "lbessel_tables.h"
 
 namespace lbessel {
@@ -43,6 +44,16 @@ __device__ __forceinline__ const LB_CONST_AS T *opaque_const(const T *p) {
 }
 
 // ---------------------------------------------------------------------------
+// Elementary functions: binary64 through the short sequences of
+// lbessel_fastmath.hpp, binary32 through the device library (hardware
+// v_exp_f32 / v_log_f32 based).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lexp(double a) { return fm::exp64(a); }
+__device__ __forceinline__ double llog(double a) { return fm::log64(a); }
+__device__ __forceinline__ float lexp(float a) { return expf(a); }
+__device__ __forceinline__ float llog(float a) { return logf(a); }
+
+// ---------------------------------------------------------------------------
 // Constants
 // ---------------------------------------------------------------------------
 
@@ -55,6 +66,7 @@ template <> struct Cst<double> {
     static constexpr double ln2 = 0x1.62e42fefa39efp-1;
     static constexpr double series_eps = 0x1p-56;  // relative truncation
     static constexpr double big_z = 1e150;         // sqrt(1+z^2) == z beyond
+    static constexpr double tiny_z = 1e-290;       // x/v may have lost bits below
 };
 template <> struct Cst<float> {
     static constexpr float log_2pi = 0x1.d67f1cp+0f;
@@ -64,6 +76,7 @@ template <> struct Cst<float> {
     static constexpr float ln2 = 0x1.62e430p-1f;
     static constexpr float series_eps = 0x1p-27f;
     static constexpr float big_z = 1e18f;
+    static constexpr float tiny_z = 1e-30f;
 };
 
 // Regime thresholds.  Shapes of Table 1:
@@ -150,16 +163,17 @@ __device__ __forceinline__ T br_mu20(T v, T x) {
     T s = T(0);
 #pragma unroll
     for (int k = 1; k <= tables::kMuTerms; ++k) {
-        // (mu - (2k-1)^2) / k = fma(mu, 1/k, -(2k-1)^2/k)
-        const T d = fma(mu, hk[2 * (k - 1)], -hk[2 * (k - 1) + 1]);
+        // c_k = c_{k-1} * ((mu - (2k-1)^2) * (1/k)) * q; both constants are
+        // scalar operands of the add and the multiply
+        const T d = (mu - hk[2 * (k - 1) + 1]) * hk[2 * (k - 1)];
         c = c * d * q;
         s = s + c;
     }
-    const T ls = log(fabs(T(1) + s));
+    const T ls = llog(fabs(T(1) + s));
     if (KIND == KIND_I)
-        return x - T(0.5) * (Cst<T>::log_2pi + log(x)) + ls;
+        return x - T(0.5) * (Cst<T>::log_2pi + llog(x)) + ls;
     else
-        return T(0.5) * (Cst<T>::log_pi_2 - log(x)) - x + ls;
+        return T(0.5) * (Cst<T>::log_pi_2 - llog(x)) - x + ls;
 }
 
 // ---------------------------------------------------------------------------
@@ -189,15 +203,19 @@ __device__ __forceinline__ T br_u13(T v, T x) {
 #pragma unroll
     for (int k = tables::kUTerms; k >= 1; --k) {
         const LB_CONST_AS T *row = P + 14 * (k - 1);
-        T pk = row[k];
+        T pk = fm::fma_c(row[k], p, row[k - 1]);
 #pragma unroll
-        for (int j = k - 1; j >= 0; --j)
-            pk = fma(pk, p, row[j]);
+        for (int j = k - 2; j >= 0; --j)
+            pk = fm::fma_c(pk, p, row[j]);
         acc = w * (pk + acc);
     }
-    const T eta = r + log(z / (T(1) + r));
-    const T ls = log(fabs(T(1) + acc));
-    const T lvr = log(v * r);
+    // z below the normal range (x/v < ~1e-290 in f64): log z from log x - log v
+    T lz = llog(z / (T(1) + r));
+    if (z < Cst<T>::tiny_z)
+        lz = llog(x) - llog(v) - llog(T(1) + r);
+    const T eta = r + lz;
+    const T ls = llog(fabs(T(1) + acc));
+    const T lvr = llog(v * r);
     if (KIND == KIND_I)
         return v * eta - T(0.5) * (Cst<T>::log_2pi + lvr) + ls;
     else
@@ -227,7 +245,8 @@ __device__ __forceinline__ T br_series_i(T v, T x) {
         if (den > T(2) * q && term < Cst<T>::series_eps * sum)
             break;
     }
-    return v * log(hx) - lgamma(v + T(1)) + log(sum);
+    // log(x/2) as log x - log 2: x/2 can underflow for subnormal x
+    return v * (llog(x) - Cst<T>::ln2) - lgamma(v + T(1)) + llog(sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,7 +289,7 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
     const T inv2x1 = T(1) / (x2 + T(1));
     const T us = (v < T(2)) ? T(0.5) : T(0.5) / v;
     const T ius = (v < T(2)) ? T(2) : T(2) * v;
-    const T lus = log(us);
+    const T lus = llog(us);
     const T den_h = fma(x2, us, T(1));
     const T inv2xus1 = T(1) / den_h;
     const LB_CONST_AS T *node = opaque_const<T>(&quad_nodes<T>()[0][0]);
@@ -278,18 +297,18 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
     ACC G = ACC(0), H = ACC(0);
     for (int j = 0; j < N; ++j) {
         const T u = node[3 * j], lu = node[3 * j + 1], iu = node[3 * j + 2];
-        const T ub = exp(beta * lu);
-        const T lg = (T(1) - ub) + vm * log((x2 + ub) * inv2x1) + T(7) * lu;
-        const T lh = (ius - iu) - tv1 * (lu - lus) + vm * log(fma(x2, u, T(1)) * inv2xus1);
+        const T ub = lexp(beta * lu);
+        const T lg = (T(1) - ub) + vm * llog((x2 + ub) * inv2x1) + T(7) * lu;
+        const T lh = (ius - iu) - tv1 * (lu - lus) + vm * llog(fma(x2, u, T(1)) * inv2xus1);
         const T w = (j >= N - NT) ? wt[j - (N - NT)] : T(1);
-        G = fma(ACC(w), ACC(exp(lg)), G);
-        H = fma(ACC(w), ACC(exp(lh)), H);
+        G = fma(ACC(w), ACC(lexp(lg)), G);
+        H = fma(ACC(w), ACC(lexp(lh)), H);
     }
-    const T mg = log(beta) - T(1) + vm * log(x2 + T(1));
-    const T mh = -ius - tv1 * lus + vm * log(den_h);
+    const T mg = llog(beta) - T(1) + vm * llog(x2 + T(1));
+    const T mh = -ius - tv1 * lus + vm * llog(den_h);
     const T m = fmax(mg, mh);
-    const T li = -Cst<T>::log_n + m + log(T(G * ACC(exp(mg - m)) + H * ACC(exp(mh - m))));
-    return Cst<T>::half_log_pi - lgamma(v + T(0.5)) - v * log(x2) - x + li;
+    const T li = -Cst<T>::log_n + m + llog(T(G * ACC(lexp(mg - m)) + H * ACC(lexp(mh - m))));
+    return Cst<T>::half_log_pi - lgamma(v + T(0.5)) - v * llog(x2) - x + li;
 }
 
 // ---------------------------------------------------------------------------

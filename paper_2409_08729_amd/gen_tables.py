@@ -194,16 +194,16 @@ def render_header() -> str:
             vals = [fmt(conv(c)) for c in row] + ["0"] * (U_TERMS - k)
             lines.append("    {" + ", ".join(vals) + "},")
         lines.append("};")
-    # Hankel expansion: c_k = c_{k-1} (mu - (2k-1)^2) / k * s/(8x), k = 1..20,
-    # evaluated as fma(mu, 1/k, -(2k-1)^2/k): rows {1/k, (2k-1)^2/k}.
+    # Hankel expansion: c_k = c_{k-1} (mu - (2k-1)^2) / k * s/(8x), k = 1..20:
+    # rows {1/k, (2k-1)^2}.
     lines.append("")
-    lines.append("// Hankel recurrence constants, row k-1 = {1/k, (2k-1)^2/k}, k = 1..20.")
+    lines.append("// Hankel recurrence constants, row k-1 = {1/k, (2k-1)^2}, k = 1..20.")
     for name, conv, fmt, ty in (("kHankel64", to_f64, f64_hex, "double"),
                                 ("kHankel32", to_f32_exact, f32_hex, "float")):
         lines.append(f"__constant__ const {ty} {name}[{MU_TERMS}][2] = {{")
         for k in range(1, MU_TERMS + 1):
             lines.append("    {" + fmt(conv(Fraction(1, k))) + ", "
-                         + fmt(conv(Fraction((2 * k - 1) ** 2, k))) + "},")
+                         + fmt(conv(Fraction((2 * k - 1) ** 2))) + "},")
         lines.append("};")
     # quadrature: right-end weights that differ from 1 (trapezoid + Gregory)
     w = trapezoid_gregory_weights()
