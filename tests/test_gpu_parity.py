@@ -349,3 +349,21 @@ def test_full_size_sampled(lb, oracle, which, kind):
     e = cond_err(y, hi, lo, v[idx], x[idx])
     print(f"{which} {kind} n={v.size}: {summary(e)}")
     assert e.max() <= TOL64
+
+
+def test_golden_closed_forms(lb):
+    """The HIP path against the stored 40-digit half-integer closed forms."""
+    from decimal import Decimal
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "closed_forms.tsv")
+    rows = [ln.rstrip("\n").split("\t") for ln in open(path) if not ln.startswith("#")]
+    for kind in ("I", "K"):
+        sel = [r for r in rows if r[0] == kind]
+        v = np.array([float(r[1]) for r in sel])
+        x = np.array([float(r[2]) for r in sel])
+        y = run(lb, kind, v, x)
+        for i, r in enumerate(sel):
+            ref = Decimal(r[3])
+            err = abs(Decimal(float(y[i])) - ref) / max(abs(ref), Decimal(1) + Decimal(
+                float(np.hypot(v[i], x[i]))))
+            assert err <= Decimal(TOL64), (kind, v[i], x[i], float(err))
