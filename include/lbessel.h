@@ -18,7 +18,8 @@
  *  - Pointers named v, x, gout, kappa, out, gx are DEVICE pointers owned by
  *    the caller, each to n contiguous elements (kappa: n, v/x: n).  Outputs
  *    must not overlap inputs.  The library allocates nothing and keeps no
- *    state between calls; calls are safe from several host threads.
+ *    state between calls; calls are safe from several host threads (the vMF
+ *    column sum takes a caller-provided workspace).
  *  - stream is a hipStream_t passed as void*; NULL means the null stream.
  *    Every call only enqueues work on that stream and returns; the caller
  *    synchronises before reading out.
@@ -133,6 +134,25 @@ int lbessel_vmf_log_norm_f32(const float *kappa, float p, float *out,
  */
 int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out,
                                   int64_t n, void *stream);
+
+/*
+ * Column sums of the L2-normalised rows of a feature matrix, the mean
+ * resultant of the vMF fit (paper, Sec. "Metric learning", eq. mean direction
+ * estimate: xbar = (1/N) sum_i x_i / ||x_i||, R = ||xbar||):
+ *   colsum[j] = sum_{i < n} X[i, j] / ||X[i, :]||_2      (zero rows add 0)
+ * X: device, row-major float32, n rows of p columns (n <= 2^31 - 1).
+ * colsum: device, p doubles.  sumsq: device, 1 double receiving
+ * sum_j colsum[j]^2 (so R = sqrt(sumsq) / n), or NULL.  Accumulation is
+ * binary64 in a fixed order, so the results are the same on every call.
+ * work: device workspace of at least lbessel_vmf_colsum_workspace(n, p)
+ * bytes, owned by the caller (contents on return are unspecified).
+ * lbessel_vmf_colsum_workspace returns that size in bytes, or a negative
+ * status for negative n or p.
+ */
+int64_t lbessel_vmf_colsum_workspace(int64_t n, int64_t p);
+int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
+                           double *sumsq, void *work, int64_t work_bytes,
+                           void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Diagnostics                                                             */

@@ -9,7 +9,8 @@ is not on a GPU, the call raises.
 log_iv(v, x), log_kv(v, x)                 log I_v(x), log K_v(x)
 log_iv_grad_x(v, x, g), log_kv_grad_x(..)  g * d/dx log I_v(x), log K_v(x)
 vmf_log_norm(kappa, p), vmf_log_norm_grad  log C_p(kappa) and d/dkappa
-LogIv, LogKv                               torch.autograd.Function wrappers
+LogIv, LogKv, VmfLogNorm                   torch.autograd.Function wrappers
+vmf_colsum(X)                              column sums of L2-normalised rows
 classify(kind, v, x), eval_branch(...),    diagnostics
 eval_ungrouped(kind, v, x)
 """
@@ -58,6 +59,7 @@ def _load():
         "lbessel_classify": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_eval_branch_f64": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_eval_ungrouped": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_vmf_colsum_f32": [vp, i64, i64, vp, vp, vp, i64, vp],
         "lbessel_abi_version": [],
         "lbessel_status_string": [ctypes.c_int],
     }
@@ -66,6 +68,8 @@ def _load():
         fn.argtypes = args
         fn.restype = ctypes.c_int
     lib.lbessel_status_string.restype = ctypes.c_char_p
+    lib.lbessel_vmf_colsum_workspace.argtypes = [i64, i64]
+    lib.lbessel_vmf_colsum_workspace.restype = i64
     _lib = lib
     return lib
 
@@ -173,6 +177,27 @@ def vmf_log_norm_grad(kappa: torch.Tensor, p: float) -> torch.Tensor:
     return out
 
 
+def vmf_colsum(X: torch.Tensor):
+    """(colsum, sumsq): column sums (float64, (p,)) of the L2-normalised rows of
+    X (N, p) float32, and their sum of squares (float64, (1,))."""
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2:
+        raise LbesselError("X must be a 2-D float32 tensor on a GPU")
+    X = X.contiguous()
+    n, p = X.shape
+    lib = _load()
+    nbytes = lib.lbessel_vmf_colsum_workspace(n, p)
+    if nbytes < 0:
+        raise LbesselError("invalid vMF shape")
+    out = torch.empty(p, dtype=torch.float64, device=X.device)
+    ss = torch.empty(1, dtype=torch.float64, device=X.device)
+    work = torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device=X.device)
+    with torch.cuda.device(X.device):
+        _check(lib.lbessel_vmf_colsum_f32(X.data_ptr(), n, p, out.data_ptr(), ss.data_ptr(),
+                                          work.data_ptr(), work.numel(), _stream(X)),
+               "lbessel_vmf_colsum_f32")
+    return out, ss
+
+
 def classify(kind: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     """Branch index per element (0 mu20, 1 u13, 2 fallback, 3 special)."""
     v, x = _prep(v, x)
@@ -240,3 +265,18 @@ class LogKv(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             raise LbesselError("the derivative in the order v is not provided")
         return None, log_kv_grad_x(v, x, g.contiguous())
+
+
+class VmfLogNorm(torch.autograd.Function):
+    """log C_p(kappa) (float64) with d/dkappa = -I_{p/2}(kappa) / I_{p/2-1}(kappa)."""
+
+    @staticmethod
+    def forward(ctx, kappa, p):
+        ctx.save_for_backward(kappa)
+        ctx.p = float(p)
+        return vmf_log_norm(kappa, p)
+
+    @staticmethod
+    def backward(ctx, g):
+        (kappa,) = ctx.saved_tensors
+        return g * vmf_log_norm_grad(kappa, ctx.p), None

@@ -294,21 +294,91 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
     const T inv2xus1 = T(1) / den_h;
     const LB_CONST_AS T *node = opaque_const<T>(&quad_nodes<T>()[0][0]);
     const LB_CONST_AS T *wt = opaque_const<T>(gregory_tail<T>());
-    ACC G = ACC(0), H = ACC(0);
-    for (int j = 0; j < N; ++j) {
+    // log g(u_j) - log g(1) and log h(u_j) - log h(u*) at node j
+    auto terms = [&](int j, T &eg, T &eh) {
         const T u = node[3 * j], lu = node[3 * j + 1], iu = node[3 * j + 2];
         const T ub = lexp(beta * lu);
         const T lg = (T(1) - ub) + vm * llog((x2 + ub) * inv2x1) + T(7) * lu;
         const T lh = (ius - iu) - tv1 * (lu - lus) + vm * llog(fma(x2, u, T(1)) * inv2xus1);
-        const T w = (j >= N - NT) ? wt[j - (N - NT)] : T(1);
-        G = fma(ACC(w), ACC(lexp(lg)), G);
-        H = fma(ACC(w), ACC(lexp(lh)), H);
+        eg = lexp(lg);
+        eh = lexp(lh);
+    };
+    ACC G = ACC(0), H = ACC(0);
+    // interior nodes: unit weight
+    for (int j = 0; j < N - NT; ++j) {
+        T eg, eh;
+        terms(j, eg, eh);
+        G += ACC(eg);
+        H += ACC(eh);
+    }
+    // last NT nodes: trapezoid + Gregory end weights
+    for (int j = N - NT; j < N; ++j) {
+        T eg, eh;
+        terms(j, eg, eh);
+        const ACC w = ACC(wt[j - (N - NT)]);
+        G = fma(w, ACC(eg), G);
+        H = fma(w, ACC(eh), H);
     }
     const T mg = llog(beta) - T(1) + vm * llog(x2 + T(1));
     const T mh = -ius - tv1 * lus + vm * llog(den_h);
     const T m = fmax(mg, mh);
     const T li = -Cst<T>::log_n + m + llog(T(G * ACC(lexp(mg - m)) + H * ACC(lexp(mh - m))));
     return Cst<T>::half_log_pi - lgamma(v + T(0.5)) - v * llog(x2) - x + li;
+}
+
+// ---------------------------------------------------------------------------
+// K_v at tiny x and small v (sub-case of the K fallback)
+// ---------------------------------------------------------------------------
+// For v < 0.3 the g part of the integrand behaves like u^a, a = 7 - 8(1-2v)/(1+2v)
+// (a < 4.8), between u ~ (2x)^{1/beta} and 1; once x < ~1e-15 that scale falls
+// below the node spacing 1/600 and the 600-node rule loses mass (at v = 0,
+// x = 1e-300 the integral is off by a factor ~6).  Below x = 1e-10 the
+// two-term small-argument form is exact to O(x^2) (DLMF 10.27.4 with the
+// leading terms of the series of I_{+-v}):
+//   K_v(x) = [Gamma(1+v) y^{-v} - Gamma(1-v) y^{v}] / (2v),  y = x/2
+//          = Gamma(1+v) L sinhc(vL) - e^{-vL} D(v),  L = log(2/x),
+//   D(v) = (Gamma(1-v) - Gamma(1+v)) / (2v) = e^{E(v)} q(v) sinhc(v q(v)),
+// with log Gamma(1+v) = -gamma v + sum_{k>=2} (-1)^k zeta(k) v^k / k split into
+// its even part E(v) and odd part -v q(v) (DLMF 5.7.3).  Both terms of K are
+// positive-dominated (first >= L > 23, second < 0.6): no cancellation.
+__device__ __forceinline__ double sinhc64(double t) {   // sinh(t)/t, t >= 0
+    if (t < 0.5) {
+        const double t2 = t * t;
+        double s = fma(t2, 1.0 / 156.0, 1.0);
+        s = fma(t2 * (1.0 / 110.0), s, 1.0);
+        s = fma(t2 * (1.0 / 72.0), s, 1.0);
+        s = fma(t2 * (1.0 / 42.0), s, 1.0);
+        s = fma(t2 * (1.0 / 20.0), s, 1.0);
+        return fma(t2 * (1.0 / 6.0), s, 1.0);
+    }
+    return (fm::exp64(t) - fm::exp64(-t)) / (2.0 * t);
+}
+
+__device__ __forceinline__ double br_k_tiny_x(double v, double x) {
+    const double L = Cst<double>::ln2 - fm::log64(x);
+    const double t = v * L;
+    double d;
+    if (v < 0.05) {
+        const double v2 = v * v;
+        // q = gamma + zeta(3) v^2/3 + zeta(5) v^4/5 + ... + zeta(11) v^10/11
+        double q = fma(v2, 0x1.0020631be48b3p+0 / 11.0, 0x1.00839f3d816b5p+0 / 9.0);
+        q = fma(v2, q, 0x1.02232da14cf39p+0 / 7.0);
+        q = fma(v2, q, 0x1.097418eca7ccep+0 / 5.0);
+        q = fma(v2, q, 0x1.33ba004f00621p+0 / 3.0);
+        q = fma(v2, q, 0x1.2788cfc6fb619p-1);
+        // E = zeta(2) v^2/2 + zeta(4) v^4/4 + ... + zeta(12) v^12/12
+        double e = fma(v2, 0x1.001020a5b2cd3p+0 / 12.0, 0x1.00412e33a5bb9p+0 / 10.0);
+        e = fma(v2, e, 0x1.010b36af86397p+0 / 8.0);
+        e = fma(v2, e, 0x1.0470984c09245p+0 / 6.0);
+        e = fma(v2, e, 0x1.151322ac7d848p+0 / 4.0);
+        e = fma(v2, e, 0x1.a51a6625307d3p+0 / 2.0);
+        e = e * v2;
+        d = fm::exp64(e) * q * sinhc64(v * q);
+    } else {
+        d = (tgamma(1.0 - v) - tgamma(1.0 + v)) / (2.0 * v);
+    }
+    const double k = tgamma(1.0 + v) * L * sinhc64(t) - fm::exp64(-t) * d;
+    return fm::log64(k);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,6 +395,8 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x) {
         return br_u13<T, KIND>(v, x);
     if (KIND == KIND_I)
         return br_series_i<T>(v, x);
+    if (x < T(1e-10) && v < T(0.3))
+        return T(br_k_tiny_x(double(v), double(x)));
     return br_quad_k<T, double>(v, x);
 }
 

@@ -327,6 +327,78 @@ __global__ __launch_bounds__(kThreads) void k_branch(int b, const double *v, con
     out[i] = y;
 }
 
+// ---------------------------------------------------------------------------
+// von Mises-Fisher mean resultant: column sums of L2-normalised rows
+// ---------------------------------------------------------------------------
+
+// inv[i] = 1 / ||X[i, :]||_2 (0 for a zero row); one workgroup per row, sum of
+// squares in binary64, fixed reduction order.
+__global__ __launch_bounds__(kThreads) void k_rownorm_inv(const float *__restrict__ X, int64_t p,
+                                                          double *__restrict__ inv) {
+    const int64_t row = blockIdx.x;
+    const float *r = X + row * p;
+    double ss = 0.0;
+    for (int64_t j = threadIdx.x; j < p; j += kThreads) {
+        const double a = r[j];
+        ss = fma(a, a, ss);
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        ss += __shfl_down(ss, off);
+    __shared__ double part[kWaves];
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = (part[0] + part[1]) + (part[2] + part[3]);
+        inv[row] = (t > 0.0) ? 1.0 / sqrt(t) : 0.0;
+    }
+}
+
+// part[r, j] = sum over rows i of slice r of X[i, j] * inv[i] (binary64).
+__global__ __launch_bounds__(kThreads) void k_colsum_part(const float *__restrict__ X,
+                                                          const double *__restrict__ inv,
+                                                          int64_t n, int64_t p, int64_t rows_per,
+                                                          double *__restrict__ part) {
+    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (j >= p)
+        return;
+    const int64_t r0 = int64_t(blockIdx.y) * rows_per;
+    const int64_t r1 = (r0 + rows_per < n) ? r0 + rows_per : n;
+    double s = 0.0;
+    for (int64_t i = r0; i < r1; ++i)
+        s = fma(double(X[i * p + j]), inv[i], s);
+    part[int64_t(blockIdx.y) * p + j] = s;
+}
+
+// colsum[j] = sum_r part[r, j] in slice order.
+__global__ __launch_bounds__(kThreads) void k_colsum_final(const double *__restrict__ part,
+                                                           int64_t nslices, int64_t p,
+                                                           double *__restrict__ colsum) {
+    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (j >= p)
+        return;
+    double s = 0.0;
+    for (int64_t r = 0; r < nslices; ++r)
+        s += part[r * p + j];
+    colsum[j] = s;
+}
+
+// *out = sum_j colsum[j]^2, one workgroup, fixed order.
+__global__ __launch_bounds__(kThreads) void k_sumsq(const double *__restrict__ c, int64_t p,
+                                                    double *__restrict__ out) {
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < p; j += kThreads)
+        s = fma(c[j], c[j], s);
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_down(s, off);
+    __shared__ double part[kWaves];
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *out = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
 }  // namespace lbessel
 
 // ===========================================================================
@@ -508,6 +580,55 @@ int lbessel_eval_ungrouped(int kind, int precision, const void *v, const void *x
         return run_ungrouped<float, KIND_I>((const float *)v, (const float *)x, (float *)out, n,
                                             s);
     return run_ungrouped<float, KIND_K>((const float *)v, (const float *)x, (float *)out, n, s);
+}
+
+// Row slices of the column-sum pass: enough workgroups to fill the chip
+// (>= 2048) while every slice keeps >= 64 rows.
+static int64_t vmf_slices(int64_t n, int64_t p) {
+    const int64_t col_blocks = (p + kThreads - 1) / kThreads;
+    int64_t r = (2048 + col_blocks - 1) / col_blocks;
+    const int64_t max_r = (n + 63) / 64;
+    if (r > max_r)
+        r = max_r;
+    if (r < 1)
+        r = 1;
+    if (r > 65535)
+        r = 65535;
+    return r;
+}
+
+int64_t lbessel_vmf_colsum_workspace(int64_t n, int64_t p) {
+    if (n < 0 || p < 0)
+        return LBESSEL_EINVAL;
+    return (vmf_slices(n, p) * p + n) * int64_t(sizeof(double));
+}
+
+int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum, double *sumsq,
+                           void *work, int64_t work_bytes, void *s) {
+    if (n < 0 || p < 0 || n > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    if (p == 0)
+        return LBESSEL_OK;
+    const int64_t need = lbessel_vmf_colsum_workspace(n, p);
+    if (colsum == nullptr || work == nullptr || work_bytes < need || (n > 0 && X == nullptr))
+        return LBESSEL_EINVAL;
+    const int64_t slices = vmf_slices(n, p);
+    const int64_t rows_per = (n + slices - 1) / slices;
+    const int64_t col_blocks = (p + kThreads - 1) / kThreads;
+    if (col_blocks > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    double *part = static_cast<double *>(work);
+    double *inv = part + slices * p;
+    hipStream_t st = static_cast<hipStream_t>(s);
+    if (n > 0)
+        hipLaunchKernelGGL(k_rownorm_inv, dim3(uint32_t(n)), dim3(kThreads), 0, st, X, p, inv);
+    hipLaunchKernelGGL(k_colsum_part, dim3(uint32_t(col_blocks), uint32_t(slices)),
+                       dim3(kThreads), 0, st, X, inv, n, p, rows_per, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3(uint32_t(col_blocks)), dim3(kThreads), 0, st, part,
+                       slices, p, colsum);
+    if (sumsq != nullptr)
+        hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(kThreads), 0, st, colsum, p, sumsq);
+    return launch_status();
 }
 
 int lbessel_abi_version(void) { return LBESSEL_ABI_VERSION; }

@@ -68,3 +68,16 @@ def corner_v100_x01(n: int, seed: int = 9):
 def band(n: int, vlo: float, vhi: float, xlo: float, xhi: float, seed: int = 10):
     g = rng(seed)
     return g.uniform(vlo, vhi, n), g.uniform(xlo, xhi, n)
+
+
+def vmf_features(n: int, p: int, seed: int, device="cpu"):
+    """Synthetic feature rows |g|, g ~ N(mu, 0.5^2 I), mu ~ N(0, I) fixed per set
+    (float32, not normalised: the library normalises each row).  Generated
+    with torch's seeded generator on `device` (reproducible per device type)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    mu = torch.randn(p, generator=gen, device=device, dtype=torch.float32)
+    X = torch.randn(n, p, generator=gen, device=device, dtype=torch.float32)
+    X.mul_(0.5).add_(mu).abs_()
+    return X
