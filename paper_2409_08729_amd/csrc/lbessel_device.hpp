@@ -52,6 +52,9 @@ __device__ __forceinline__ double lexp(double a) { return fm::exp64(a); }
 __device__ __forceinline__ double llog(double a) { return fm::log64(a); }
 __device__ __forceinline__ float lexp(float a) { return expf(a); }
 __device__ __forceinline__ float llog(float a) { return logf(a); }
+// exp of an argument known to satisfy |a| < 1e9
+__device__ __forceinline__ double lexp_b(double a) { return fm::exp64_bounded(a); }
+__device__ __forceinline__ float lexp_b(float a) { return expf(a); }
 
 // ---------------------------------------------------------------------------
 // Constants
@@ -297,11 +300,13 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
     // log g(u_j) - log g(1) and log h(u_j) - log h(u*) at node j
     auto terms = [&](int j, T &eg, T &eh) {
         const T u = node[3 * j], lu = node[3 * j + 1], iu = node[3 * j + 2];
-        const T ub = lexp(beta * lu);
+        // arguments of the exponentials are bounded: beta log u in [-103, 0];
+        // the log-ratios are finite sums of terms below ~1e5 in size
+        const T ub = lexp_b(beta * lu);
         const T lg = (T(1) - ub) + vm * llog((x2 + ub) * inv2x1) + T(7) * lu;
         const T lh = (ius - iu) - tv1 * (lu - lus) + vm * llog(fma(x2, u, T(1)) * inv2xus1);
-        eg = lexp(lg);
-        eh = lexp(lh);
+        eg = lexp_b(lg);
+        eh = lexp_b(lh);
     };
     ACC G = ACC(0), H = ACC(0);
     // interior nodes: unit weight

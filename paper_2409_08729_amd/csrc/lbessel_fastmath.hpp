@@ -42,16 +42,27 @@ __host__ __device__ __forceinline__ float fma_c(float a, float b, float c) {
 #endif
 }
 
+// 1/d to ~2^-100 relative from the hardware reciprocal and one Newton step
+// (the host build divides).  Only used where the quotient feeds a small
+// correction term.
+__host__ __device__ __forceinline__ double rcp_nr(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double q = __builtin_amdgcn_rcp(d);
+    return fma(q, fma(-d, q, 1.0), q);
+#else
+    return 1.0 / d;
+#endif
+}
+
 // ln 2 = kLn2Hi + kLn2Lo, kLn2Hi with 32 significant bits (k * kLn2Hi exact
 // for |k| < 2^21).
 constexpr double kLog2e = 0x1.71547652b82fep+0;
 constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
 constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
 
-// exp(y) for finite y: 2^k e^r, k = rint(y log2 e), r = y - k ln 2 in
-// [-ln2/2, ln2/2], e^r by a degree-11 polynomial (relative error 3e-18).
-// y below about -745 gives 0, y above about 709.8 gives +inf.
-__host__ __device__ __forceinline__ double exp64(double y) {
+// 2^k e^r with k = rint(y log2 e), r = y - k ln 2 in [-ln2/2, ln2/2]; e^r by a
+// degree-11 polynomial (relative error 3e-18).  Returns (e^r, k).
+__host__ __device__ __forceinline__ double exp64_core(double y, double &k_out) {
     const double k = rint(y * kLog2e);
     double r = fma(-k, kLn2Hi, y);
     r = fma(-k, kLn2Lo, r);
@@ -66,10 +77,26 @@ __host__ __device__ __forceinline__ double exp64(double y) {
     p = fma_c(p, r, 0x1.0000000000011p-1);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
+    k_out = k;
+    return p;
+}
+
+// exp(y) for finite y; below about -745 gives 0, above about 709.8 +inf.
+__host__ __device__ __forceinline__ double exp64(double y) {
+    double k;
+    const double p = exp64_core(y, k);
     // clamp the exponent so the conversion is defined; beyond +-1100 the
     // scaling over/underflows to inf/0 exactly as the true value does
     const double kc = fmin(fmax(k, -1100.0), 1100.0);
     return ldexp(p, int(kc));
+}
+
+// exp(y) for |y| < 1e9 (the exponent fits an int without clamping); values
+// below about -745 still underflow to 0 through the final scaling.
+__host__ __device__ __forceinline__ double exp64_bounded(double y) {
+    double k;
+    const double p = exp64_core(y, k);
+    return ldexp(p, int(k));
 }
 
 // log(a) for finite a > 0 (normal or subnormal).  a = m 2^e with m in
@@ -83,7 +110,7 @@ __host__ __device__ __forceinline__ double log64(double a) {
     m = low ? m + m : m;
     e = low ? e - 1 : e;
     const double f = m - 1.0;
-    const double s = f / (2.0 + f);
+    const double s = f * rcp_nr(2.0 + f);
     const double z = s * s;
     double p = fma_c(0x1.2b584aae78a57p-3, z, 0x1.39fe606542ddep-3);
     p = fma_c(p, z, 0x1.7462b4ab2ef6bp-3);
