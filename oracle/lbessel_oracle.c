@@ -320,7 +320,7 @@ static qf ktrap(const kint *p, qf h, qf tpk, qf ref)
     return logq(h) + logq(s);
 }
 
-/* log of int_0^inf exp(kphi(t)) dt, or NaN if the step halving stalls */
+/* log of int_0^inf exp(kphi(t)) dt, or NaN if ten step halvings do not settle */
 static qf klog_integral(const kint *p)
 {
     const qf tpk = kpeak(p);
@@ -330,7 +330,7 @@ static qf klog_integral(const kint *p)
     if (h > 0.05Q)
         h = 0.05Q;
     qf prev = ktrap(p, h, tpk, fmax);
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < 10; ++it) {       /* converges in one or two */
         h /= 2;
         const qf cur = ktrap(p, h, tpk, fmax);
         if (fabsq(cur - prev) <= TRAP_AGREE * fmaxq(1, fabsq(fmax)))

@@ -22,15 +22,36 @@ _LIB = os.path.join(_HERE, "liblbessel_oracle.so")
 _lib = None
 
 
+def compile_oracle(src: str, out: str) -> str:
+    """gcc -O2 with OpenMP and libquadmath: src (C) -> out (.so)."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wno-unknown-pragmas", src, "-o", tmp, "-lquadmath", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP + libquadmath); returns the .so path."""
+    """Compile the oracle; returns the .so path."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lquadmath", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        compile_oracle(_SRC, _LIB)
     return _LIB
+
+
+def open_library(path: str):
+    """ctypes handle of an oracle build at `path` with argument types set."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for name in ("lbo_log_iv", "lbo_log_kv", "lbo_dlog_iv", "lbo_dlog_kv"):
+        fn = getattr(lib, name)
+        fn.argtypes = [dp, dp, dp, dp, ctypes.c_int64]
+        fn.restype = None
+    lib.lbo_vmf_log_norm.argtypes = [dp, ctypes.c_double, dp, dp, ctypes.c_int64]
+    lib.lbo_vmf_log_norm.restype = None
+    lib.lbo_max_threads.restype = ctypes.c_int
+    lib.lbo_set_threads.argtypes = [ctypes.c_int]
+    return lib
 
 
 def _load():
@@ -38,25 +59,40 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        for name in ("lbo_log_iv", "lbo_log_kv", "lbo_dlog_iv", "lbo_dlog_kv"):
-            fn = getattr(lib, name)
-            fn.argtypes = [dp, dp, dp, dp, ctypes.c_int64]
-            fn.restype = None
-        lib.lbo_vmf_log_norm.argtypes = [dp, ctypes.c_double, dp, dp, ctypes.c_int64]
-        lib.lbo_vmf_log_norm.restype = None
-        lib.lbo_max_threads.restype = ctypes.c_int
-        lib.lbo_set_threads.argtypes = [ctypes.c_int]
-        _lib = lib
+        _lib = open_library(_LIB)
     return _lib
+
+
+class Oracle:
+    """The same functions as this module, bound to the build at `path`."""
+
+    def __init__(self, path: str):
+        self._lib = open_library(path)
+
+    def _map2(self, name, v, x):
+        return _map2(name, v, x, self._lib)
+
+    def log_iv(self, v, x):
+        return self._map2("lbo_log_iv", v, x)
+
+    def log_kv(self, v, x):
+        return self._map2("lbo_log_kv", v, x)
+
+    def dlog_iv(self, v, x):
+        return self._map2("lbo_dlog_iv", v, x)
+
+    def dlog_kv(self, v, x):
+        return self._map2("lbo_dlog_kv", v, x)
+
+    def vmf_log_norm(self, kappa, p):
+        return vmf_log_norm(kappa, p, self._lib)
 
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _map2(name: str, v, x):
+def _map2(name: str, v, x, lib=None):
     v = np.ascontiguousarray(v, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
     v, x = np.broadcast_arrays(v, x)
@@ -64,7 +100,7 @@ def _map2(name: str, v, x):
     x = np.ascontiguousarray(x).ravel()
     hi = np.empty_like(v)
     lo = np.empty_like(v)
-    getattr(_load(), name)(_ptr(v), _ptr(x), _ptr(hi), _ptr(lo), v.size)
+    getattr(lib or _load(), name)(_ptr(v), _ptr(x), _ptr(hi), _ptr(lo), v.size)
     return hi, lo
 
 
@@ -88,12 +124,12 @@ def dlog_kv(v, x):
     return _map2("lbo_dlog_kv", v, x)
 
 
-def vmf_log_norm(kappa, p: float):
+def vmf_log_norm(kappa, p: float, lib=None):
     """log C_p(kappa) of the von Mises-Fisher density."""
     k = np.ascontiguousarray(kappa, dtype=np.float64).ravel()
     hi = np.empty_like(k)
     lo = np.empty_like(k)
-    _load().lbo_vmf_log_norm(_ptr(k), float(p), _ptr(hi), _ptr(lo), k.size)
+    (lib or _load()).lbo_vmf_log_norm(_ptr(k), float(p), _ptr(hi), _ptr(lo), k.size)
     return hi, lo
 
 
