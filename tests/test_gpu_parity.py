@@ -152,7 +152,7 @@ def test_huge_arguments_match_leading_terms(lb):
     yi = run(lb, "I", v, x)
     yk = run(lb, "K", v, x)
     assert np.isfinite(yi).all() and np.isfinite(yk).all()
-    np.testing.assert_allclose(yi, x - 0.5 * np.log(2 * np.pi * x), rtol=4e-16)
+    np.testing.assert_allclose(yi, x - 0.5 * (np.log(2 * np.pi) + np.log(x)), rtol=4e-16)
     np.testing.assert_allclose(yk, 0.5 * (np.log(np.pi / 2) - np.log(x)) - x, rtol=4e-16)
     # tiny x, huge v: log I -> v log(x/2) - lgamma(v+1), finite
     v = np.array([1e4, 1e8, 1e12])
