@@ -13,7 +13,12 @@ roofline of the dominant kernel (log K f64: plain VALU arithmetic), the f32
 path on the same inputs rounded to f32, and the binary128 oracle timed on a
 bounded sample on the host cores (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline] [--no-f32]
+The serving section replays a seeded Poisson request stream through the
+native server (batched vs one launch per request) and reports p50/p99
+latency and throughput at several offered loads.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+                    [--no-f32] [--no-vmf] [--no-serving]
 """
 from __future__ import annotations
 
@@ -92,30 +97,60 @@ def op_counts(lb, torch, sets):
 
 def cpu_baseline(sets_host, seconds_target=12.0):
     """The binary128 oracle on a uniform random sample of the same workload
-    (equal share per set, doubling until ~seconds_target of work)."""
+    (equal share per set, doubling until ~seconds_target of work).  Returns
+    the baseline record and the sample with its reference values, so the GPU
+    outputs of the timed step can be checked on the same points."""
     from oracle import oracle
     rng = np.random.default_rng(5)
     per_set, total_pairs, total_t = 64, 0, 0.0
+    sample = []
     while total_t < seconds_target and per_set <= 1 << 16:
-        vs, xs = [], []
-        for v, x in sets_host:
+        vs, xs, ids = [], [], []
+        for j, (v, x) in enumerate(sets_host):
             idx = rng.integers(0, v.size, per_set)
             vs.append(v[idx])
             xs.append(x[idx])
+            ids.append((j, idx))
         v = np.concatenate(vs)
         x = np.concatenate(xs)
         t = time.perf_counter()
-        oracle.log_iv(v, x)
-        oracle.log_kv(v, x)
+        ri = oracle.log_iv(v, x)
+        rk = oracle.log_kv(v, x)
         total_t += time.perf_counter() - t
         total_pairs += v.size
+        sample.append((ids, v, x, ri, rk))
         per_set *= 2
     n = 2 * total_pairs
-    return {"value": n / total_t / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"{total_pairs} pairs drawn uniformly, equal share from each of the 12 sets "
-                      f"(11 orders + stress grid), log I and log K each, binary128, "
-                      f"{total_t:.1f} s"}
+    rec = {"value": n / total_t / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
+           "kind": "oracle",
+           "sample": f"{total_pairs} pairs drawn uniformly, equal share from each of the 12 sets "
+                     f"(11 orders + stress grid), log I and log K each, binary128, "
+                     f"{total_t:.1f} s"}
+    return rec, sample
+
+
+def sample_errors(torch, outs, sample):
+    """Largest error of the timed step's f64 outputs on the oracle sample:
+    |y - ref| / max(|ref|, 1 + |(v, x)|) (the parity measure) and the plain
+    relative error |y - ref| / |ref|, per function."""
+    res = {}
+    for kind, col in (("I", 3), ("K", 4)):
+        worst_c, worst_r, npts = 0.0, 0.0, 0
+        for blk in sample:
+            ids, v, x = blk[0], blk[1], blk[2]
+            hi, lo = blk[col]
+            got = np.concatenate([outs[(j, kind)][torch.from_numpy(idx).to(outs[(j, kind)].device)]
+                                  .cpu().numpy() for j, idx in ids])
+            fin = np.isfinite(hi)
+            d = np.abs((got[fin] - hi[fin]) - lo[fin])
+            den = np.maximum(np.abs(hi[fin]), 1.0 + np.hypot(v[fin], x[fin]))
+            worst_c = max(worst_c, float((d / den).max(initial=0.0)))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                rel = np.where(hi[fin] != 0, d / np.abs(hi[fin]), 0.0)
+            worst_r = max(worst_r, float(rel.max(initial=0.0)))
+            npts += int(fin.sum())
+        res[kind] = {"max_cond_err": worst_c, "max_rel_err": worst_r, "points": npts}
+    return res
 
 
 def vmf_bench(lb, torch, n=50_000, dims=(2048, 8192, 32768)):
@@ -154,6 +189,87 @@ def vmf_bench(lb, torch, n=50_000, dims=(2048, 8192, 32768)):
     return out
 
 
+def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
+    """Open-loop Poisson request stream through the native server: uneven
+    evaluation requests (host arrays, 1 .. 4M pairs, I/K, f64/f32) and vMF
+    fits (device features, p in {2048, 8192, 32768}, N in [1e3, 5e4]).
+    Saturation = all requests offered at once; then offered loads at the
+    given fractions of the batched server's saturation rate.  Latency =
+    completion - scheduled arrival."""
+    from paper_2409_08729_amd import serve, workloads as wl
+    reqs, gaps = wl.serving_requests(count)
+    v, x = wl.serving_pool()
+    pools = {64: (torch.from_numpy(v).pin_memory(), torch.from_numpy(x).pin_memory()),
+             32: (torch.from_numpy(v.astype(np.float32)).pin_memory(),
+                  torch.from_numpy(x.astype(np.float32)).pin_memory())}
+    feats = {p: wl.vmf_features(wl.SERVE_VMF_ROWS[1], p, seed=p, device="cuda:0")
+             for p in wl.SERVE_VMF_DIMS}
+    tot = {64: 0, 32: 0}
+    for r in reqs:
+        if r["type"] == "eval":
+            tot[r["precision"]] += r["n"]
+    outbuf = {64: torch.empty(tot[64], dtype=torch.float64, pin_memory=True),
+              32: torch.empty(tot[32], dtype=torch.float32, pin_memory=True)}
+    results = torch.empty((count, 4), dtype=torch.float64, pin_memory=True)
+    base, at = [], {64: 0, 32: 0}
+    for i, r in enumerate(reqs):
+        if r["type"] == "eval":
+            pv, px = pools[r["precision"]]
+            o, n = r["offset"], r["n"]
+            a = at[r["precision"]]
+            at[r["precision"]] += n
+            base.append({"type": "eval", "kind": r["kind"], "v": pv[o:o + n], "x": px[o:o + n],
+                         "out": outbuf[r["precision"]][a:a + n]})
+        else:
+            base.append({"type": "vmf", "X": feats[r["p"]][: r["N"]], "result": results[i]})
+    pairs = sum(r["n"] for r in reqs if r["type"] == "eval")
+    modes = (("batched", "batched", 4), ("plain", "plain", 1), ("plain_4streams", "plain", 4))
+
+    def run(label, times):
+        _, mode, streams = [m for m in modes if m[0] == label][0]
+        items = [dict(b, t=float(t)) for b, t in zip(base, times)]
+        with serve.Server(mode, streams=streams, arena_bytes=4 << 30) as srv:
+            infos = srv.replay(items, timeout=600)
+            st = srv.stats()
+        lat = np.array([i["t_done"] - i["t_arrival"] for i in infos]) * 1e3
+        span = max(i["t_done"] for i in infos) - min(i["t_arrival"] for i in infos)
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                "requests_per_s": count / span, "G_evals_s": pairs / span / 1e9,
+                "span_s": span, "batches": st["batches"], "kernel_launches": st["kernel_launches"],
+                "max_batch_requests": st["max_batch_requests_seen"],
+                "arena_peak_MiB": st["arena_peak_bytes"] / 2**20, "queue_peak": st["queue_peak"]}
+
+    zeros = np.zeros(count)
+    run("batched", zeros)                                   # warm-up (pages, code objects)
+    run("plain", zeros)
+    sat = {}
+    for label, _, _ in modes:
+        log(f"serving: saturation, {label}")
+        sat[label] = run(label, zeros)
+    unit_t = np.cumsum(gaps)
+    sweep = []
+    for f in loads:
+        qps = f * sat["batched"]["requests_per_s"]
+        row = {"load": f, "offered_requests_per_s": qps}
+        for label, _, _ in modes:
+            log(f"serving: load {f:.2f} ({qps:.0f} req/s), {label}")
+            row[label] = run(label, unit_t / qps)
+        sweep.append(row)
+    n_vmf = sum(r["type"] == "vmf" for r in reqs)
+    return {"requests": count, "eval_requests": count - n_vmf, "vmf_requests": n_vmf,
+            "eval_pairs": pairs,
+            "mix": "eval: n log-uniform [1, 4M], kind I/K and f64/f32 equally likely, "
+                   "log10 v ~ U[-3,4] (1/256 of v = 0), log10 x ~ U[-3,4], host pinned "
+                   "in/out; vMF (1/8 of requests): p in {2048, 8192, 32768}, N log-uniform "
+                   "[1e3, 5e4], features on the device",
+            "modes": {"batched": "FIFO memory admission, continuous batching into segmented "
+                                 "launches, 4 batches in flight",
+                      "plain": "same queue, one request at a time, one launch per request",
+                      "plain_4streams": "one launch per request, 4 requests in flight"},
+            "saturation": sat, "sweep": sweep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +278,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-vmf", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -265,14 +382,23 @@ def main():
     if not args.no_vmf:
         vmf_res = vmf_bench(lb, torch)
 
-    cpu = None
+    cpu, errors = None, None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         host = [(v.cpu().numpy(), x.cpu().numpy()) for _, v, x in sets]
-        cpu = cpu_baseline(host)
+        cpu, sample = cpu_baseline(host)
+        del host
+        errors = sample_errors(torch, outs, sample)
+
+    serving = None
+    if not args.no_serving:
+        del outs
+        torch.cuda.empty_cache()
+        serving = serving_bench(torch)
 
     line = {
-        "metric": "G evals/s log I_v & log K_v (f64)",
+        "metric": "G evals/s log I_v & log K_v (f64, f32) at max rel err; "
+                  "p50/p99 latency at QPS",
         "value": value,
         "unit": "G evals/s",
         "n_gpus": 1,
@@ -291,11 +417,13 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "all_finite": finite,
+        "max_err_on_oracle_sample": errors,
         "ms_I_per_step": i_ms,
         "ms_K_per_step": k_ms,
         "f32": f32,
         "grouping_ablation": ablation,
         "vmf": vmf_res,
+        "serving": serving,
         "kernels": kern,
     }
     print(json.dumps(line), flush=True)

@@ -154,6 +154,54 @@ int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
                            double *sumsq, void *work, int64_t work_bytes,
                            void *stream);
 
+/*
+ * Maximum-likelihood vMF concentration on the device (paper, Sec. "Metric
+ * learning", eqs. kappa estimates and the Newton update): the column sums
+ * above, then R = sqrt(sumsq)/n, kappa_0 = R (p - R^2) / (1 - R^2) and
+ * Newton steps kappa <- kappa - (A_p - R) / (1 - A_p^2 - (p-1) A_p / kappa)
+ * with A_p = I_{p/2}(kappa) / I_{p/2-1}(kappa) from the same evaluation code
+ * as lbessel_log_iv_f64, until a step is below 1e-15 relative (at most 40).
+ * result: device, 4 doubles {kappa, R, kappa_0, Newton steps}; kappa is NaN
+ * when R is 0 or 1 (all rows zero, or all rows parallel).
+ * work: device workspace of lbessel_vmf_fit_workspace(n, p) bytes.
+ */
+int64_t lbessel_vmf_fit_workspace(int64_t n, int64_t p);
+int lbessel_vmf_fit_f32(const float *X, int64_t n, int64_t p, double *result,
+                        void *work, int64_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Segmented evaluation (many independent arrays in one launch)            */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One array of a segmented launch: n pairs at v, x (device), results to out
+ * (device), all of the launch's precision.  tile0 is the first workgroup
+ * tile of the segment: the running sum of lbessel_segment_tiles(n) over the
+ * segments before it (the first segment has tile0 = 0).
+ */
+typedef struct lbessel_segment {
+    const void *v;
+    const void *x;
+    void *out;
+    int64_t n;
+    int64_t tile0;
+} lbessel_segment_t;
+
+/* Workgroup tiles covering n elements in a segmented launch (n >= 0). */
+int64_t lbessel_segment_tiles(int64_t n);
+
+/*
+ * Forward log I (kind 0) or log K (kind 1) of every segment in one launch of
+ * tiles workgroups; precision 64 or 32.  segs: DEVICE array of nseg
+ * descriptors sorted by tile0; tiles: total tile count (tile0 of the last
+ * segment plus its own tiles).  Each result equals what
+ * lbessel_log_{iv,kv}_{f64,f32} gives for the segment alone, bit for bit.
+ * This is the batching primitive of the serving runtime (lbessel_serve.h):
+ * many small requests fill the chip in one launch.
+ */
+int lbessel_eval_segments(int kind, int precision, const lbessel_segment_t *segs,
+                          int nseg, int64_t tiles, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Diagnostics                                                             */
 /* ---------------------------------------------------------------------- */

@@ -11,6 +11,8 @@ log_iv_grad_x(v, x, g), log_kv_grad_x(..)  g * d/dx log I_v(x), log K_v(x)
 vmf_log_norm(kappa, p), vmf_log_norm_grad  log C_p(kappa) and d/dkappa
 LogIv, LogKv, VmfLogNorm                   torch.autograd.Function wrappers
 vmf_colsum(X)                              column sums of L2-normalised rows
+vmf_fit(X)                                 device kappa solve (kappa, R, kappa_0, steps)
+eval_segments(kind, vs, xs)                many arrays in one segmented launch
 classify(kind, v, x), eval_branch(...),    diagnostics
 eval_ungrouped(kind, v, x)
 """
@@ -60,6 +62,8 @@ def _load():
         "lbessel_eval_branch_f64": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_eval_ungrouped": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_vmf_colsum_f32": [vp, i64, i64, vp, vp, vp, i64, vp],
+        "lbessel_vmf_fit_f32": [vp, i64, i64, vp, vp, i64, vp],
+        "lbessel_eval_segments": [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, i64, vp],
         "lbessel_abi_version": [],
         "lbessel_status_string": [ctypes.c_int],
     }
@@ -68,8 +72,11 @@ def _load():
         fn.argtypes = args
         fn.restype = ctypes.c_int
     lib.lbessel_status_string.restype = ctypes.c_char_p
-    lib.lbessel_vmf_colsum_workspace.argtypes = [i64, i64]
-    lib.lbessel_vmf_colsum_workspace.restype = i64
+    for name in ("lbessel_vmf_colsum_workspace", "lbessel_vmf_fit_workspace"):
+        getattr(lib, name).argtypes = [i64, i64]
+        getattr(lib, name).restype = i64
+    lib.lbessel_segment_tiles.argtypes = [i64]
+    lib.lbessel_segment_tiles.restype = i64
     _lib = lib
     return lib
 
@@ -196,6 +203,64 @@ def vmf_colsum(X: torch.Tensor):
                                           work.data_ptr(), work.numel(), _stream(X)),
                "lbessel_vmf_colsum_f32")
     return out, ss
+
+
+def vmf_fit(X: torch.Tensor):
+    """Maximum-likelihood vMF concentration of the rows of X (N, p) float32,
+    solved on the device: (kappa, R, kappa_0, newton_steps) as Python floats."""
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2:
+        raise LbesselError("X must be a 2-D float32 tensor on a GPU")
+    X = X.contiguous()
+    n, p = X.shape
+    lib = _load()
+    nbytes = lib.lbessel_vmf_fit_workspace(n, p)
+    if nbytes < 0:
+        raise LbesselError("invalid vMF shape")
+    res = torch.empty(4, dtype=torch.float64, device=X.device)
+    work = torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device=X.device)
+    with torch.cuda.device(X.device):
+        _check(lib.lbessel_vmf_fit_f32(X.data_ptr(), n, p, res.data_ptr(), work.data_ptr(),
+                                       work.numel(), _stream(X)), "lbessel_vmf_fit_f32")
+    k, R, k0, steps = res.cpu().tolist()
+    return k, R, k0, int(steps)
+
+
+class Segment(ctypes.Structure):
+    """lbessel_segment_t of include/lbessel.h."""
+    _fields_ = [("v", ctypes.c_void_p), ("x", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("tile0", ctypes.c_int64)]
+
+
+def eval_segments(kind: str, vs, xs):
+    """log I or log K of several (v, x) array pairs in ONE segmented launch;
+    returns the list of outputs (each equals log_iv/log_kv of that pair)."""
+    if len(vs) != len(xs):
+        raise LbesselError("vs and xs must have the same length")
+    pairs = [_prep(v, x) for v, x in zip(vs, xs)]
+    if not pairs:
+        return []
+    dev, dt = pairs[0][1].device, pairs[0][1].dtype
+    if any(x.device != dev or x.dtype != dt for _, x in pairs):
+        raise LbesselError("all segments must share one device and dtype")
+    lib = _load()
+    outs = [torch.empty_like(x) for _, x in pairs]
+    table = (Segment * len(pairs))()
+    tiles = 0
+    k = 0
+    for (v, x), o in zip(pairs, outs):
+        if x.numel() == 0:
+            continue
+        table[k] = Segment(v.data_ptr(), x.data_ptr(), o.data_ptr(), x.numel(), tiles)
+        tiles += lib.lbessel_segment_tiles(x.numel())
+        k += 1
+    host = torch.frombuffer(bytearray(bytes(table)), dtype=torch.uint8)
+    dseg = host.to(dev)
+    prec = 64 if dt == torch.float64 else 32
+    with torch.cuda.device(dev):
+        _check(lib.lbessel_eval_segments(KIND[kind], prec, dseg.data_ptr(), k, tiles,
+                                         _stream(dseg)), "lbessel_eval_segments")
+        torch.cuda.current_stream(dev).synchronize()   # table and outputs live until here
+    return outs
 
 
 def classify(kind: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:

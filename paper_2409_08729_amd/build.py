@@ -3,7 +3,9 @@
     python -m paper_2409_08729_amd.build
 
 Generates csrc/lbessel_tables.h from exact rationals, then compiles
-csrc/lbessel_kernels.hip with hipcc into paper_2409_08729_amd/liblbessel.so.
+csrc/lbessel_kernels.hip (the kernels and their C-ABI) and
+csrc/lbessel_serve.cpp (the serving runtime) with hipcc into
+paper_2409_08729_amd/liblbessel.so.
 """
 from __future__ import annotations
 
@@ -51,7 +53,8 @@ def build(out: str = LIB, extra: list[str] | None = None) -> str:
     tmp = out + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []),
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "lbessel_kernels.hip"), "-o", tmp]
+           os.path.join(CSRC, "lbessel_kernels.hip"),
+           os.path.join(CSRC, "lbessel_serve.cpp"), "-lpthread", "-o", tmp]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)

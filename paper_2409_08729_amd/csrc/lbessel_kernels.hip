@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include "lbessel.h"
+#include "lbessel_serve.h"
 #include "lbessel_device.hpp"
 
 namespace lbessel {
@@ -155,8 +156,9 @@ __device__ __forceinline__ int rank_below(uint64_t m) {
                                      __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
 }
 
+// One tile (workgroup-wide: every thread of the workgroup must call it).
 template <typename T, int KIND, int OP>
-__global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
+__device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     constexpr int NV = OpTraits<OP>::nv;
     constexpr int EPT = TileCfg<NV>::ept;
     constexpr int TILE = TileCfg<NV>::tile;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int64_t base = int64_t(blockIdx.x) * TILE;
+    const int64_t base = tile * TILE;
 
     // 1. load, screen, classify.  code: 2 bits per evaluation slot
     //    (slot = r * NV + sub), BR_NONE = nothing to evaluate.
@@ -299,6 +301,38 @@ __global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
     }
 }
 
+template <typename T, int KIND, int OP>
+__global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
+    grouped_tile<T, KIND, OP>(a, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Segmented grouped kernel: many independent arrays in one launch (the
+// serving runtime's batches).  Segment s owns the tiles from segs[s].tile0
+// up to the next segment's tile0; each tile is the same grouped_tile as in
+// the single-array kernel, so every result equals the single-array one.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_grouped_seg(
+    const lbessel_segment_t *__restrict__ segs, int nseg) {
+    const int64_t t = blockIdx.x;
+    // largest s with segs[s].tile0 <= t (uniform across the workgroup)
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].tile0 <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const lbessel_segment_t sg = segs[lo];
+    if (t < sg.tile0)   // malformed table: leave the tile alone (workgroup-uniform)
+        return;
+    Args<T> a{static_cast<const T *>(sg.v), static_cast<const T *>(sg.x), nullptr,
+              static_cast<T *>(sg.out), sg.n, T(0), T(0)};
+    grouped_tile<T, KIND, OP_LOG>(a, t - sg.tile0);
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics kernels
 // ---------------------------------------------------------------------------
@@ -397,6 +431,39 @@ __global__ __launch_bounds__(kThreads) void k_sumsq(const double *__restrict__ c
     __syncthreads();
     if (threadIdx.x == 0)
         *out = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// Maximum-likelihood kappa of a vMF fit from the column-sum pass (paper,
+// eq. kappa estimates): R = sqrt(sumsq) / n, kappa_0 = R (p - R^2)/(1 - R^2),
+// then kappa <- F(kappa) with A_p = exp(log I_{p/2} - log I_{p/2-1}) from the
+// same branch code as the forward path, until the step is below 1e-15
+// relative (at most 40 steps).  One lane; out = {kappa, R, kappa_0, steps}.
+__global__ __launch_bounds__(64) void k_vmf_kappa(const double *__restrict__ sumsq, int64_t n,
+                                                  double p, double *__restrict__ out) {
+    if (threadIdx.x != 0)
+        return;
+    const double R = sqrt(*sumsq) / double(n);
+    const double v = 0.5 * p - 1.0;
+    double k = R * (p - R * R) / (1.0 - R * R);
+    const double k0 = k;
+    int it = 0;
+    bool ok = (R > 0.0) && (R < 1.0) && (n > 0);
+    for (; ok && it < 40; ++it) {
+        const double l0 = eval_full<double, KIND_I>(v, k);
+        const double l1 = eval_full<double, KIND_I>(v + 1.0, k);
+        const double A = exp(l1 - l0);
+        const double kn = k - (A - R) / (1.0 - A * A - (p - 1.0) * A / k);
+        const bool stop = fabs(kn - k) <= 1e-15 * fabs(kn);
+        k = kn;
+        if (stop) {
+            ++it;
+            break;
+        }
+    }
+    out[0] = ok ? k : __builtin_nan("");
+    out[1] = R;
+    out[2] = k0;
+    out[3] = double(it);
 }
 
 }  // namespace lbessel
@@ -631,6 +698,60 @@ int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
     return launch_status();
 }
 
+int lbessel_vmf_fit_f32(const float *X, int64_t n, int64_t p, double *result, void *work,
+                        int64_t work_bytes, void *s) {
+    if (n < 1 || p < 2 || result == nullptr)
+        return LBESSEL_EINVAL;
+    const int64_t need = lbessel_vmf_colsum_workspace(n, p);
+    if (work == nullptr || work_bytes < need + int64_t((p + 1) * sizeof(double)))
+        return LBESSEL_EINVAL;
+    double *colsum = reinterpret_cast<double *>(static_cast<char *>(work) + need);
+    double *sumsq = colsum + p;
+    const int rc = lbessel_vmf_colsum_f32(X, n, p, colsum, sumsq, work, need, s);
+    if (rc != LBESSEL_OK)
+        return rc;
+    hipLaunchKernelGGL(k_vmf_kappa, dim3(1), dim3(64), 0, static_cast<hipStream_t>(s), sumsq, n,
+                       double(p), result);
+    return launch_status();
+}
+
+int64_t lbessel_vmf_fit_workspace(int64_t n, int64_t p) {
+    const int64_t w = lbessel_vmf_colsum_workspace(n, p);
+    return (w < 0) ? w : w + (p + 1) * int64_t(sizeof(double));
+}
+
+int lbessel_eval_segments(int kind, int precision, const lbessel_segment_t *segs, int nseg,
+                          int64_t tiles, void *s) {
+    if ((kind != 0 && kind != 1) || (precision != 64 && precision != 32) || nseg < 0 ||
+        tiles < 0 || tiles > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    if (nseg == 0 || tiles == 0)
+        return LBESSEL_OK;
+    if (segs == nullptr)
+        return LBESSEL_EINVAL;
+    const lbessel_segment_t *sg = segs;
+    hipStream_t st = static_cast<hipStream_t>(s);
+    const dim3 grid{uint32_t(tiles)}, block{kThreads};
+    if (precision == 64) {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_grouped_seg<double, KIND_I>), grid, block, 0, st, sg, nseg);
+        else
+            hipLaunchKernelGGL((k_grouped_seg<double, KIND_K>), grid, block, 0, st, sg, nseg);
+    } else {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_grouped_seg<float, KIND_I>), grid, block, 0, st, sg, nseg);
+        else
+            hipLaunchKernelGGL((k_grouped_seg<float, KIND_K>), grid, block, 0, st, sg, nseg);
+    }
+    return launch_status();
+}
+
+int64_t lbessel_segment_tiles(int64_t n) {
+    if (n < 0)
+        return LBESSEL_EINVAL;
+    return (n + TileCfg<1>::tile - 1) / TileCfg<1>::tile;
+}
+
 int lbessel_abi_version(void) { return LBESSEL_ABI_VERSION; }
 
 const char *lbessel_status_string(int status) {
@@ -639,6 +760,9 @@ const char *lbessel_status_string(int status) {
     case LBESSEL_EINVAL: return "invalid argument";
     case LBESSEL_EHIP: return "HIP launch failure";
     case LBESSEL_ENODEV: return "no usable device";
+    case LBESSEL_ETOOBIG: return "request larger than the server arena";
+    case LBESSEL_ETIMEOUT: return "timed out";
+    case LBESSEL_ESTOPPED: return "server stopped";
     default: return "unknown status";
     }
 }

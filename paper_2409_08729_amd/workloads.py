@@ -81,3 +81,48 @@ def vmf_features(n: int, p: int, seed: int, device="cpu"):
     X = torch.randn(n, p, generator=gen, device=device, dtype=torch.float32)
     X.mul_(0.5).add_(mu).abs_()
     return X
+
+
+# ---------------------------------------------------------------------------
+# Serving request stream
+# ---------------------------------------------------------------------------
+SEED_SERVE = 20240916
+SERVE_MAX_PAIRS = 4 << 20          # evaluation requests: 1 .. 4M pairs
+SERVE_VMF_DIMS = (2048, 8192, 32768)
+SERVE_VMF_ROWS = (1000, 50_000)    # N log-uniform in this range
+
+
+def serving_pool(n: int = 2 * SERVE_MAX_PAIRS, seed: int = SEED_SERVE):
+    """(v, x) float64 pools that evaluation requests slice: log10 v ~ U[-3, 4],
+    log10 x ~ U[-3, 4], and one element in 256 with v = 0 exactly."""
+    g = rng(seed)
+    v = 10.0 ** g.uniform(-3.0, 4.0, n)
+    x = 10.0 ** g.uniform(-3.0, 4.0, n)
+    v[g.integers(0, n, n // 256)] = 0.0
+    return v, x
+
+
+def serving_requests(count: int, seed: int = SEED_SERVE + 1, vmf_share: float = 0.125,
+                     pool: int = 2 * SERVE_MAX_PAIRS, max_pairs: int = SERVE_MAX_PAIRS,
+                     vmf_rows=SERVE_VMF_ROWS):
+    """A seeded request stream: a list of dicts and the unit-rate Poisson
+    inter-arrival gaps (divide by the offered requests/s to get seconds).
+      evaluation: {'type': 'eval', 'kind': 'I'|'K', 'precision': 64|32,
+                   'n': log-uniform integer in [1, max_pairs], 'offset': start in the pool}
+      vMF fit:    {'type': 'vmf', 'p': one of SERVE_VMF_DIMS,
+                   'N': log-uniform integer in vmf_rows}"""
+    g = rng(seed)
+    reqs = []
+    for _ in range(count):
+        if g.random() < vmf_share:
+            p = int(SERVE_VMF_DIMS[g.integers(0, len(SERVE_VMF_DIMS))])
+            lo, hi = np.log(vmf_rows[0]), np.log(vmf_rows[1])
+            N = int(np.clip(np.round(np.exp(g.uniform(lo, hi))), vmf_rows[0], vmf_rows[1]))
+            reqs.append({"type": "vmf", "p": p, "N": N})
+        else:
+            n = int(np.clip(np.floor(np.exp(g.uniform(0.0, np.log(max_pairs + 1.0)))), 1, max_pairs))
+            reqs.append({"type": "eval", "kind": "IK"[int(g.integers(0, 2))],
+                         "precision": (64, 32)[int(g.integers(0, 2))], "n": n,
+                         "offset": int(g.integers(0, pool - n + 1))})
+    gaps = g.exponential(1.0, count)
+    return reqs, gaps

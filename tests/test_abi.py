@@ -1,5 +1,5 @@
 """C-ABI surface, host only: the library loads, exports every symbol that
-include/lbessel.h declares, and rejects bad arguments before any GPU call."""
+include/*.h declares, and rejects bad arguments before any GPU call."""
 import ctypes
 import os
 import re
@@ -7,13 +7,20 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbessel.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbessel.h", "lbessel_serve.h")]
 
 
 def declared_symbols():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbessel_\w+)\s*\(", text)))
+    found = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        found.update(re.findall(r"\b(lbessel_\w+)\s*\(", text))
+    return sorted(found)
+
+
+def test_headers_are_the_whole_include_dir():
+    names = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert names == sorted(os.path.basename(h) for h in HEADERS)
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +31,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     syms = declared_symbols()
-    assert len(syms) >= 15
+    assert len(syms) >= 30
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -34,6 +41,8 @@ def test_version_and_status(lib):
     assert lib.lbessel_status_string(0) == b"ok"
     assert lib.lbessel_status_string(-1) == b"invalid argument"
     assert lib.lbessel_status_string(-2) == b"HIP launch failure"
+    assert lib.lbessel_status_string(-4) == b"request larger than the server arena"
+    assert lib.lbessel_status_string(-5) == b"timed out"
     assert lib.lbessel_status_string(12345) == b"unknown status"
 
 
@@ -74,3 +83,27 @@ def test_binding_refuses_cpu_tensors():
     import paper_2409_08729_amd as lb
     with pytest.raises(lb.LbesselError):
         lb.log_iv(torch.ones(4, dtype=torch.float64), torch.ones(4, dtype=torch.float64))
+
+
+def test_segment_and_fit_argument_checks(lib):
+    lib.lbessel_segment_tiles.restype = ctypes.c_int64
+    lib.lbessel_segment_tiles.argtypes = [ctypes.c_int64]
+    assert [lib.lbessel_segment_tiles(n) for n in (0, 1, 2048, 2049)] == [0, 1, 1, 2]
+    assert lib.lbessel_segment_tiles(-1) == -1
+    assert lib.lbessel_eval_segments(0, 64, None, 0, 0, None) == 0         # empty batch
+    assert lib.lbessel_eval_segments(2, 64, None, 0, 0, None) == -1        # bad kind
+    assert lib.lbessel_eval_segments(0, 64, None, 3, 5, None) == -1        # NULL table
+    lib.lbessel_vmf_fit_f32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p]
+    assert lib.lbessel_vmf_fit_f32(None, 0, 8, None, None, 0, None) == -1  # n < 1
+    assert lib.lbessel_vmf_fit_f32(None, 10, 8, None, None, 0, None) == -1
+
+
+def test_server_needs_a_device():
+    import torch
+    from paper_2409_08729_amd import serve
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible: covered by the GPU serving tests")
+    with pytest.raises(Exception, match="no usable device"):
+        serve.Server()
