@@ -178,12 +178,19 @@ def vmf_bench(lb, torch, n=50_000, dims=(2048, 8192, 32768)):
         t = time.perf_counter()
         k_lbfgs = vmf.fit_kappa_lbfgs(R, p)
         t_lbfgs = time.perf_counter() - t
+        lb.vmf_fit(X)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        k_dev, _, _, steps_dev = lb.vmf_fit(X)      # column sums + device Newton, result on host
+        t_dev = time.perf_counter() - t
         nbytes = 2 * X.numel() * 4          # row-norm pass + column-sum pass
         out[str(p)] = {"N": n, "colsum_ms": ms, "hbm_GBs": nbytes / ms / 1e6,
                        "hbm_frac": nbytes / ms / 1e6 / 8000.0, "R": R,
                        "kappa_0": ks[0], "kappa_1": ks[1], "kappa_2": ks[2] if len(ks) > 2 else None,
                        "kappa": ks[-1], "newton_steps": len(ks) - 1, "newton_s": t_newton,
-                       "kappa_lbfgs": k_lbfgs, "lbfgs_s": t_lbfgs}
+                       "kappa_lbfgs": k_lbfgs, "lbfgs_s": t_lbfgs,
+                       "device_fit": {"kappa": k_dev, "newton_steps": steps_dev,
+                                      "ms": t_dev * 1e3}}
         del X, colsum, sumsq
         torch.cuda.empty_cache()
     return out

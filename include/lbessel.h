@@ -160,7 +160,9 @@ int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
  * above, then R = sqrt(sumsq)/n, kappa_0 = R (p - R^2) / (1 - R^2) and
  * Newton steps kappa <- kappa - (A_p - R) / (1 - A_p^2 - (p-1) A_p / kappa)
  * with A_p = I_{p/2}(kappa) / I_{p/2-1}(kappa) from the same evaluation code
- * as lbessel_log_iv_f64, until a step is below 1e-15 relative (at most 40).
+ * as lbessel_log_iv_f64, until a step is below 1e-15 relative or no longer
+ * shrinks (the noise floor: A_p has a relative error of ~kappa * 1e-16, so
+ * kappa is defined to ~1e-11 relative at p ~ 1e4), at most 40 steps.
  * result: device, 4 doubles {kappa, R, kappa_0, Newton steps}; kappa is NaN
  * when R is 0 or 1 (all rows zero, or all rows parallel).
  * work: device workspace of lbessel_vmf_fit_workspace(n, p) bytes.

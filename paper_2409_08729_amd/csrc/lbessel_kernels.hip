@@ -437,7 +437,9 @@ __global__ __launch_bounds__(kThreads) void k_sumsq(const double *__restrict__ c
 // eq. kappa estimates): R = sqrt(sumsq) / n, kappa_0 = R (p - R^2)/(1 - R^2),
 // then kappa <- F(kappa) with A_p = exp(log I_{p/2} - log I_{p/2-1}) from the
 // same branch code as the forward path, until the step is below 1e-15
-// relative (at most 40 steps).  One lane; out = {kappa, R, kappa_0, steps}.
+// relative or no longer shrinks (the noise floor of A_p, whose two log-values
+// are of size ~kappa), at most 40 steps.  One lane; out = {kappa, R, kappa_0,
+// steps}.
 __global__ __launch_bounds__(64) void k_vmf_kappa(const double *__restrict__ sumsq, int64_t n,
                                                   double p, double *__restrict__ out) {
     if (threadIdx.x != 0)
@@ -447,13 +449,16 @@ __global__ __launch_bounds__(64) void k_vmf_kappa(const double *__restrict__ sum
     double k = R * (p - R * R) / (1.0 - R * R);
     const double k0 = k;
     int it = 0;
+    double prev = __builtin_inf();
     bool ok = (R > 0.0) && (R < 1.0) && (n > 0);
     for (; ok && it < 40; ++it) {
         const double l0 = eval_full<double, KIND_I>(v, k);
         const double l1 = eval_full<double, KIND_I>(v + 1.0, k);
         const double A = exp(l1 - l0);
         const double kn = k - (A - R) / (1.0 - A * A - (p - 1.0) * A / k);
-        const bool stop = fabs(kn - k) <= 1e-15 * fabs(kn);
+        const double d = fabs(kn - k);
+        const bool stop = (d <= 1e-15 * fabs(kn)) || (d >= prev);
+        prev = d;
         k = kn;
         if (stop) {
             ++it;

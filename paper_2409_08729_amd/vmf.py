@@ -38,17 +38,25 @@ def a_p(kappa: float, p: float, device="cuda:0") -> float:
 
 def kappa_estimates(R: float, p: float, steps: int = 8, device="cuda:0") -> list[float]:
     """[kappa_0, kappa_1, ...]: kappa_0 then Newton steps F until the update is
-    below 1e-15 relative (at most `steps`)."""
+    below 1e-15 relative or stops shrinking (at most `steps`).
+
+    The second test ends the iteration at its noise floor: A_p comes from two
+    log-values of size ~kappa, so it carries a relative error of ~kappa * 1e-16,
+    and with A_p'(kappa) ~ 1e-2 / p the root is only defined to ~1e-11 relative
+    for the vMF fits here; past that point Newton updates no longer contract."""
     if not (0.0 < R < 1.0):
         raise ValueError("mean resultant length must be in (0, 1)")
     k = R * (p - R * R) / (1.0 - R * R)
     out = [k]
+    prev = math.inf
     for _ in range(steps):
         A = a_p(k, p, device)
         k_new = k - (A - R) / (1.0 - A * A - (p - 1.0) * A / k)
         out.append(k_new)
-        if abs(k_new - k) <= 1e-15 * abs(k_new):
+        d = abs(k_new - k)
+        if d <= 1e-15 * abs(k_new) or d >= prev:
             break
+        prev = d
         k = k_new
     return out
 
