@@ -86,13 +86,15 @@ def one_step(lb, torch, sets, outs, timers=None):
 
 
 def op_counts(lb, torch, sets):
-    """Branch mix of every set (lbessel_classify) for the op model."""
-    mix = {}
+    """Branch mix of every set (lbessel_classify) and the total integrand node
+    count of the K fallback elements (lbessel_k_nodes) for the op model."""
+    mix, nodes = {}, {}
     for j, (name, v, x) in enumerate(sets):
         for kind in ("I", "K"):
             b = lb.classify(kind, v, x)
             mix[(j, kind)] = torch.bincount(b.to(torch.int64), minlength=4).cpu().tolist()
-    return mix
+        nodes[j] = int(lb.k_nodes(v, x).to(torch.int64).sum().item())
+    return mix, nodes
 
 
 def cpu_baseline(sets_host, seconds_target=12.0):
@@ -196,6 +198,59 @@ def vmf_bench(lb, torch, n=50_000, dims=(2048, 8192, 32768)):
     return out
 
 
+ABLATIONS = (  # (variant, layout): the paper's own choices put back one at a time
+    ("default", "grouped"), ("default", "naive"), ("default", "sorted"),
+    ("paper_regimes", "grouped"), ("u_integral", "grouped"), ("simpson", "grouped"),
+    ("paper", "grouped"), ("paper", "sorted"), ("paper", "naive"),
+    ("seven", "naive"), ("seven", "sorted"),
+)
+
+
+def ablation_bench(lb, torch, sets, sample=1 << 13):
+    """Time and accuracy of each (variant, layout) on the stress grid and on the
+    v = 1 order set, log I and log K (binary64).  Accuracy: largest error on a
+    seeded sample of the stress grid against the binary128 oracle."""
+    from oracle import oracle
+    res = {}
+    picks = [sets[0], sets[-1]]
+    works = {}
+    for name, v, x in picks:
+        need = lb.lib().lbessel_eval_variant_workspace(v.numel())
+        works[name] = torch.empty(int(need), dtype=torch.uint8, device=v.device)
+    rng = np.random.default_rng(11)
+    _, vs, xs = sets[-1]
+    idx = torch.from_numpy(rng.integers(0, vs.numel(), sample)).to(vs.device)
+    sv, sx = vs[idx].contiguous(), xs[idx].contiguous()
+    hv, hx = sv.cpu().numpy(), sx.cpu().numpy()
+    ref = {"I": oracle.log_iv(hv, hx), "K": oracle.log_kv(hv, hx)}
+    den = 1.0 + np.hypot(hv, hx)
+    for var, lay in ABLATIONS:
+        key = f"{var}/{lay}"
+        res[key] = {}
+        for kind in ("I", "K"):
+            row = {}
+            for name, v, x in picks:
+                lb.eval_variant(kind, var, lay, v[:4096], x[:4096], works[name])
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                lb.eval_variant(kind, var, lay, v, x, works[name])
+                e1.record()
+                torch.cuda.synchronize()
+                row[f"{name}_ms"] = e0.elapsed_time(e1)
+            y = lb.eval_variant(kind, var, lay, sv, sx).cpu().numpy()
+            hi, lo = ref[kind]
+            fin = np.isfinite(hi)
+            d = np.abs((y[fin] - hi[fin]) - lo[fin]) / np.maximum(np.abs(hi[fin]), den[fin])
+            row["max_cond_err_stress_sample"] = float(d.max(initial=0.0))
+            row["frac_above_4e-15"] = float((d > 4e-15).mean())
+            res[key][kind] = row
+        log(f"ablation {key} done")
+    return {"sample": f"{sample} stress-grid points (seed 11) against the binary128 oracle",
+            "results": res}
+
+
 def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
     """Open-loop Poisson request stream through the native server: uneven
     evaluation requests (host arrays, 1 .. 4M pairs, I/K, f64/f32) and vMF
@@ -286,6 +341,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-vmf", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -324,13 +380,14 @@ def main():
 
     # roofline of the dominant kernel: log K f64, on its largest launch (the
     # stress grid); op model = per-branch VALU instructions x branch counts
-    mix = op_counts(lb, torch, sets)
+    mix, knodes = op_counts(lb, torch, sets)
     om = json.load(open(OPMODEL))
     ck = om["K_f64"]
 
     def k_ops(j):
         c = mix[(j, "K")]
-        return c[0] * ck["mu20"] + c[1] * ck["u13"] + c[2] * ck["fallback"]
+        return (c[0] * ck["mu20"] + c[1] * ck["u13"] + c[2] * ck["fallback_setup"]
+                + knodes[j] * ck["fallback_per_node"])
 
     js = len(sets) - 1
     ops = k_ops(js)
@@ -344,6 +401,9 @@ def main():
             "launch": f"{sets[js][0]}: {sets[js][1].numel()} pairs",
             "ops_per_launch": ops, "launch_ms": dur * 1e3,
             "branch_counts": dict(zip(("mu20", "u13", "fallback", "special"), mix[(js, "K")])),
+            "fallback_nodes": knodes[js],
+            "op_model": "mu20 x n_mu + u13 x n_u + fallback_setup x n_fb + "
+                        "fallback_per_node x nodes (paper_2409_08729_amd/opmodel.json)",
             "algorithmic_bytes_per_launch": 24 * sets[js][1].numel(),
             "all_K_launches": {"frac": all_ops / all_dur / 1e12 / VALU_PEAK_TOPS,
                                "ms": all_dur * 1e3}}
@@ -384,6 +444,10 @@ def main():
         dt = time.perf_counter() - t
         f32 = {"value": evals / dt / 1e9, "unit": "G evals/s", "ms_per_step": dt * 1e3}
         del sets32, o32
+
+    ablations = None
+    if not args.no_ablation:
+        ablations = ablation_bench(lb, torch, sets)
 
     vmf_res = None
     if not args.no_vmf:
@@ -429,6 +493,7 @@ def main():
         "ms_K_per_step": k_ms,
         "f32": f32,
         "grouping_ablation": ablation,
+        "ablations": ablations,
         "vmf": vmf_res,
         "serving": serving,
         "kernels": kern,

@@ -219,6 +219,14 @@ int lbessel_classify(int kind, int precision, const void *v, const void *x,
                      uint8_t *branch, int64_t n, void *stream);
 
 /*
+ * Integrand evaluations the log K fallback spends on each element (for the
+ * op model of the benchmark): the node count of its integral rule, 0 for
+ * elements of another branch or sub-case.  precision 64 or 32.
+ */
+int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
+                    int64_t n, void *stream);
+
+/*
  * Evaluate every element with one forced branch (0, 1 or 2 as above)
  * regardless of its regime, f64 only.  Used to validate each branch
  * against the reference on its own; outside a branch's regime the result is
@@ -236,6 +244,47 @@ int lbessel_eval_branch_f64(int kind, int branch, const double *v,
  */
 int lbessel_eval_ungrouped(int kind, int precision, const void *v,
                            const void *x, void *out, int64_t n, void *stream);
+
+/*
+ * Variants of the method and of the grouping, for measurement (binary64):
+ * the same forward evaluation as lbessel_log_{iv,kv}_f64 with one of the
+ * paper's own choices put back.  variant:
+ *   LBESSEL_VAR_DEFAULT        this library's path
+ *   LBESSEL_VAR_PAPER_REGIMES  Table 1 thresholds as printed (GPU subset:
+ *                              mu_20, U_13, fallback)
+ *   LBESSEL_VAR_U_INTEGRAL     K fallback by the paper's integral (eq. log Kv
+ *                              integral) on its 600 nodes, trapezoid weights
+ *                              with an order-8 Gregory end correction
+ *   LBESSEL_VAR_SIMPSON        the same integral with the composite Simpson
+ *                              1/3 rule of the paper (normalised by 1/(3N))
+ *   LBESSEL_VAR_PAPER          Table 1 GPU subset + Simpson: the paper's GPU
+ *                              method
+ *   LBESSEL_VAR_SEVEN          Algorithm 1 as run on a CPU: mu_3, mu_20, U_4,
+ *                              U_6, U_9, U_13 (Table 1), then the fallback
+ * layout: how elements meet the branches:
+ *   LBESSEL_LAYOUT_GROUPED  per-workgroup branch-sorted lists in LDS (this
+ *                           library; not for LBESSEL_VAR_SEVEN)
+ *   LBESSEL_LAYOUT_NAIVE    one element per thread, in input order
+ *   LBESSEL_LAYOUT_SORTED   global radix sort of the elements by branch
+ *                           first (the paper's GPU grouping); needs work
+ * work: device workspace of lbessel_eval_variant_workspace(n) bytes for the
+ * sorted layout (ignored otherwise).  n <= 2^31 - 1.  Variants other than
+ * the default do not meet this library's accuracy bar everywhere; that is
+ * what they are for.
+ */
+#define LBESSEL_VAR_DEFAULT 0
+#define LBESSEL_VAR_PAPER_REGIMES 1
+#define LBESSEL_VAR_U_INTEGRAL 2
+#define LBESSEL_VAR_SIMPSON 3
+#define LBESSEL_VAR_PAPER 4
+#define LBESSEL_VAR_SEVEN 5
+#define LBESSEL_LAYOUT_GROUPED 0
+#define LBESSEL_LAYOUT_NAIVE 1
+#define LBESSEL_LAYOUT_SORTED 2
+int64_t lbessel_eval_variant_workspace(int64_t n);
+int lbessel_eval_variant(int kind, int variant, int layout, const double *v,
+                         const double *x, double *out, int64_t n, void *work,
+                         int64_t work_bytes, void *stream);
 
 /* Static description of a status code. */
 const char *lbessel_status_string(int status);

@@ -59,6 +59,9 @@ def _load():
         "lbessel_vmf_log_norm_f32": [vp, ctypes.c_float, vp, i64, vp],
         "lbessel_vmf_log_norm_grad_f64": [vp, ctypes.c_double, vp, i64, vp],
         "lbessel_classify": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_k_nodes": [ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_eval_variant": [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp,
+                                 i64, vp],
         "lbessel_eval_branch_f64": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_eval_ungrouped": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_vmf_colsum_f32": [vp, i64, i64, vp, vp, vp, i64, vp],
@@ -75,6 +78,8 @@ def _load():
     for name in ("lbessel_vmf_colsum_workspace", "lbessel_vmf_fit_workspace"):
         getattr(lib, name).argtypes = [i64, i64]
         getattr(lib, name).restype = i64
+    lib.lbessel_eval_variant_workspace.argtypes = [i64]
+    lib.lbessel_eval_variant_workspace.restype = i64
     lib.lbessel_segment_tiles.argtypes = [i64]
     lib.lbessel_segment_tiles.restype = i64
     _lib = lib
@@ -263,6 +268,33 @@ def eval_segments(kind: str, vs, xs):
     return outs
 
 
+VARIANTS = {"default": 0, "paper_regimes": 1, "u_integral": 2, "simpson": 3, "paper": 4,
+            "seven": 5}
+LAYOUTS = {"grouped": 0, "naive": 1, "sorted": 2}
+
+
+def eval_variant(kind: str, variant: str, layout: str, v: torch.Tensor, x: torch.Tensor,
+                 work: torch.Tensor | None = None) -> torch.Tensor:
+    """Forward log I / log K (float64) with one of the paper's own choices put
+    back (see VARIANTS) and a chosen grouping layout (see LAYOUTS)."""
+    v, x = _prep(v, x)
+    if x.dtype != torch.float64:
+        raise LbesselError("eval_variant is float64 only")
+    lib = _load()
+    out = torch.empty_like(x)
+    if layout == "sorted" and work is None:
+        need = lib.lbessel_eval_variant_workspace(x.numel())
+        if need < 0:
+            raise LbesselError("too many elements for the sorted layout")
+        work = torch.empty(max(int(need), 8), dtype=torch.uint8, device=x.device)
+    wp, wn = (work.data_ptr(), work.numel()) if work is not None else (None, 0)
+    with torch.cuda.device(x.device):
+        _check(lib.lbessel_eval_variant(KIND[kind], VARIANTS[variant], LAYOUTS[layout],
+                                        v.data_ptr(), x.data_ptr(), out.data_ptr(), x.numel(),
+                                        wp, wn, _stream(x)), "lbessel_eval_variant")
+    return out
+
+
 def classify(kind: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     """Branch index per element (0 mu20, 1 u13, 2 fallback, 3 special)."""
     v, x = _prep(v, x)
@@ -272,6 +304,18 @@ def classify(kind: str, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
         _check(_load().lbessel_classify(KIND[kind], prec, v.data_ptr(), x.data_ptr(),
                                         out.data_ptr(), x.numel(), _stream(x)),
                "lbessel_classify")
+    return out
+
+
+def k_nodes(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Integrand evaluations of the log K fallback per element (int32; 0 for
+    elements that take another branch)."""
+    v, x = _prep(v, x)
+    out = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    prec = 64 if x.dtype == torch.float64 else 32
+    with torch.cuda.device(x.device):
+        _check(_load().lbessel_k_nodes(prec, v.data_ptr(), x.data_ptr(), out.data_ptr(),
+                                       x.numel(), _stream(x)), "lbessel_k_nodes")
     return out
 
 

@@ -145,6 +145,54 @@ __device__ __forceinline__ int classify(T v, T x) {
 }
 
 // ---------------------------------------------------------------------------
+// Variants of the method, for measurement (f64 only)
+// ---------------------------------------------------------------------------
+//   VAR_DEFAULT        the library's path
+//   VAR_PAPER_REGIMES  Table 1 thresholds as printed (GPU subset: mu_20, U_13)
+//   VAR_U_INTEGRAL     K fallback by the paper's u-integral on its 600 nodes,
+//                      trapezoid + order-8 Gregory end weights
+//   VAR_SIMPSON        the same integral with composite Simpson 1/3 weights
+//   VAR_PAPER          Table 1 GPU subset + Simpson: the paper's GPU method
+//   VAR_SEVEN          Algorithm 1's CPU ordering: mu_3, mu_20, U_4, U_6, U_9,
+//                      U_13 with Table 1 thresholds, then the fallback
+enum { VAR_DEFAULT = 0, VAR_PAPER_REGIMES = 1, VAR_U_INTEGRAL = 2, VAR_SIMPSON = 3,
+       VAR_PAPER = 4, VAR_SEVEN = 5, VAR_COUNT = 6 };
+// branch codes of VAR_SEVEN, in priority order
+enum { B7_MU3 = 0, B7_MU20 = 1, B7_U4 = 2, B7_U6 = 3, B7_U9 = 4, B7_U13 = 5, B7_FB = 6 };
+
+// Table 1 predicates (natural logarithms), both kinds.
+__device__ __forceinline__ bool paper_mu3(double v, double x) {
+    return (x > 1400.0 && v < 3.05) || (0.6229 * fm::log64(x) - 3.2318 > fm::log64(v) && v > 3.1);
+}
+__device__ __forceinline__ bool paper_mu20(double v, double x) {
+    return (x > 30.0 && v < 15.3919) ||
+           (0.5113 * fm::log64(x) + 0.7939 > fm::log64(v) && x > 59.6925);
+}
+__device__ __forceinline__ bool paper_u(double v, double x, double x0, double v0, double v1) {
+    return (x > x0 && v > v0) || (v > v1);
+}
+
+template <typename T, int KIND, int VAR>
+__device__ __forceinline__ int classify_var(T v, T x) {
+    if (VAR == VAR_PAPER_REGIMES || VAR == VAR_PAPER) {
+        const double dv = v, dx = x;
+        return paper_mu20(dv, dx) ? BR_MU
+                                  : (paper_u(dv, dx, 19.6931, 0.7, 12.6964) ? BR_U : BR_FB);
+    }
+    if (VAR == VAR_SEVEN) {
+        const double dv = v, dx = x;
+        if (paper_mu3(dv, dx)) return B7_MU3;
+        if (paper_mu20(dv, dx)) return B7_MU20;
+        if (paper_u(dv, dx, 274.2377, 0.3, 163.6993)) return B7_U4;
+        if (paper_u(dv, dx, 84.4153, 0.46, 56.9971)) return B7_U6;
+        if (paper_u(dv, dx, 35.9074, 0.6, 20.1534)) return B7_U9;
+        if (paper_u(dv, dx, 19.6931, 0.7, 12.6964)) return B7_U13;
+        return B7_FB;
+    }
+    return classify<T, KIND>(v, x);
+}
+
+// ---------------------------------------------------------------------------
 // mu_20: Hankel expansion
 // ---------------------------------------------------------------------------
 // S = 1 + sum_{k=1}^{20} c_k,  c_k = c_{k-1} (mu - (2k-1)^2) s / (8 k x),
@@ -157,15 +205,17 @@ template <> __device__ __forceinline__ const float (*hankel_table<float>())[2] {
     return tables::kHankel32;
 }
 
-template <typename T, int KIND>
-__device__ __forceinline__ T br_mu20(T v, T x) {
+// NT correction terms (mu_NT); the library uses NT = 20, the seven-branch
+// variant of Algorithm 1 also mu_3.
+template <typename T, int KIND, int NT = tables::kMuTerms>
+__device__ __forceinline__ T br_mu(T v, T x) {
     const T mu = T(4) * v * v;
     const T q = (KIND == KIND_I ? T(-0.125) : T(0.125)) / x;
     const LB_CONST_AS T *hk = opaque_const<T>(&hankel_table<T>()[0][0]);
     T c = T(1);
     T s = T(0);
 #pragma unroll
-    for (int k = 1; k <= tables::kMuTerms; ++k) {
+    for (int k = 1; k <= NT; ++k) {
         // c_k = c_{k-1} * ((mu - (2k-1)^2) * (1/k)) * q; both constants are
         // scalar operands of the add and the multiply
         const T d = (mu - hk[2 * (k - 1) + 1]) * hk[2 * (k - 1)];
@@ -194,8 +244,10 @@ template <> __device__ __forceinline__ const float (*debye_table<float>())[14] {
     return tables::kDebyeP32;
 }
 
-template <typename T, int KIND>
-__device__ __forceinline__ T br_u13(T v, T x) {
+// NT Debye terms (U_NT); the library uses NT = 13, the seven-branch variant
+// of Algorithm 1 also U_4, U_6 and U_9.
+template <typename T, int KIND, int NT = tables::kUTerms>
+__device__ __forceinline__ T br_u(T v, T x) {
     const T z = x / v;
     const T r = (z < Cst<T>::big_z) ? sqrt(fma(z, z, T(1))) : z;
     const T t = T(1) / r;
@@ -204,7 +256,7 @@ __device__ __forceinline__ T br_u13(T v, T x) {
     const LB_CONST_AS T *P = opaque_const<T>(&debye_table<T>()[0][0]);
     T acc = T(0);
 #pragma unroll
-    for (int k = tables::kUTerms; k >= 1; --k) {
+    for (int k = NT; k >= 1; --k) {
         const LB_CONST_AS T *row = P + 14 * (k - 1);
         T pk = fm::fma_c(row[k], p, row[k - 1]);
 #pragma unroll
@@ -281,7 +333,9 @@ template <> __device__ __forceinline__ const float *gregory_tail<float>() {
 }
 
 // ACC: type of the two 600-term sums (binary64 also for binary32 terms).
-template <typename T, typename ACC>
+// SIMPSON: composite Simpson 1/3 weights instead (the paper's rule, with the
+// normalisation 1/(3N) of h/3 for h = 1/N).
+template <typename T, typename ACC, bool SIMPSON = false>
 __device__ __forceinline__ T br_quad_k(T v, T x) {
     constexpr int N = tables::kQuadN;
     constexpr int NT = tables::kGregoryOrder + 1;   // nodes with weight != 1
@@ -309,20 +363,31 @@ __device__ __forceinline__ T br_quad_k(T v, T x) {
         eh = lexp_b(lh);
     };
     ACC G = ACC(0), H = ACC(0);
-    // interior nodes: unit weight
-    for (int j = 0; j < N - NT; ++j) {
-        T eg, eh;
-        terms(j, eg, eh);
-        G += ACC(eg);
-        H += ACC(eh);
-    }
-    // last NT nodes: trapezoid + Gregory end weights
-    for (int j = N - NT; j < N; ++j) {
-        T eg, eh;
-        terms(j, eg, eh);
-        const ACC w = ACC(wt[j - (N - NT)]);
-        G = fma(w, ACC(eg), G);
-        H = fma(w, ACC(eh), H);
+    if (SIMPSON) {
+        // node j is u = (j+1)/N: weight 4/3 (j+1 odd), 2/3 (even), 1/3 at u = 1
+        for (int j = 0; j < N; ++j) {
+            T eg, eh;
+            terms(j, eg, eh);
+            const ACC w = (j == N - 1) ? ACC(1.0 / 3.0) : ((j & 1) ? ACC(2.0 / 3.0) : ACC(4.0 / 3.0));
+            G = fma(w, ACC(eg), G);
+            H = fma(w, ACC(eh), H);
+        }
+    } else {
+        // interior nodes: unit weight
+        for (int j = 0; j < N - NT; ++j) {
+            T eg, eh;
+            terms(j, eg, eh);
+            G += ACC(eg);
+            H += ACC(eh);
+        }
+        // last NT nodes: trapezoid + Gregory end weights
+        for (int j = N - NT; j < N; ++j) {
+            T eg, eh;
+            terms(j, eg, eh);
+            const ACC w = ACC(wt[j - (N - NT)]);
+            G = fma(w, ACC(eg), G);
+            H = fma(w, ACC(eh), H);
+        }
     }
     const T mg = llog(beta) - T(1) + vm * llog(x2 + T(1));
     const T mh = -ius - tv1 * lus + vm * llog(den_h);
@@ -387,21 +452,127 @@ __device__ __forceinline__ double br_k_tiny_x(double v, double x) {
 }
 
 // ---------------------------------------------------------------------------
+// K_v by the trapezoid rule on the cosh integral (fallback for x >= 1e-10)
+// ---------------------------------------------------------------------------
+// K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9).  The
+// integrand is even in t and entire, and decays double-exponentially, so the
+// trapezoid rule with step h converges geometrically: its error is the
+// integrand's Fourier transform at 2 pi / h, ~ K_{v + 2 pi i / h}(x), and
+// h = min(0.22 / (1 + v/20), 0.5 / sqrt(x cosh t*)) keeps it below 1e-16
+// relative on the whole fallback region (x <= 21, v <= 14.6; fitted against
+// the binary128 oracle with a margin).  Only nodes where the log-integrand is
+// within kDrop of its value at the peak t* are summed, which takes 10 to ~150
+// nodes instead of the 600 of the rule on the u-integral.  Node positions
+// are multiples of 1/64, so every t_j is exact and the only rounding in a
+// term is that of its own exponent.  The sum is kept relative to the
+// log-integrand at the grid point nearest t* (log-sum shift).
+// nodes (may be null): receives the number of integrand evaluations.
+__device__ __forceinline__ double br_k_cosh(double v, double x, int *nodes = nullptr) {
+    constexpr double kGrid = 1.0 / 64.0;
+    constexpr double kDrop = 45.0;          // e^-45 ~ 3e-20 of the peak term
+    constexpr int kMaxNodes = 1024;         // every walk ends (window <= ~40 / h)
+    // peak: x sinh t = v tanh(v t); Newton from asinh(v/x), which lies right of
+    // the root of this convex increasing function, so iterates decrease to it
+    double t = 0.0;
+    if (v * v > x) {
+        const double q = v / x;
+        t = fm::log64(q + sqrt(fma(q, q, 1.0)));
+        for (int it = 0; it < 16; ++it) {
+            const double e = fm::exp64(t), r = fm::rcp_nr(e);
+            const double z = fm::exp64(-2.0 * v * t);
+            const double iz = fm::rcp_nr(1.0 + z);
+            const double psi = fma(0.5 * x, e - r, -v * (1.0 - z) * iz);
+            const double dpsi = fma(0.5 * x, e + r, -4.0 * v * v * z * iz * iz);
+            const double dt = psi / dpsi;
+            t = fmax(t - dt, 0.0);
+            if (fabs(dt) < 1e-4)
+                break;
+        }
+    }
+    const double et = fm::exp64(t);
+    const double ch = 0.5 * (et + fm::rcp_nr(et));
+    double h = fmin(0.22 / fma(0.05, v, 1.0), 0.5 / sqrt(x * ch));
+    h = fmax(floor(h * 64.0), 1.0) * kGrid;
+    const double t0 = rint(t * 64.0) * kGrid;
+    // shift M = log-integrand at t0 (log cosh(vt) = vt + log1p(e^{-2vt}) - ln 2)
+    const double e0 = fm::exp64(t0);
+    const double vt0 = v * t0;
+    const double M = fma(-0.5 * x, e0 + fm::rcp_nr(e0), vt0) +
+                     fm::log64(1.0 + fm::exp64(-2.0 * vt0)) - Cst<double>::ln2;
+    // F(t) = 2 exp(-x cosh t - M) cosh(v t); ap = -x cosh t + v t - M
+    auto F = [&](double tj, double &ap) -> double {
+        const double e = fm::exp64_bounded(tj);
+        const double a = fma(-0.5 * x, e + fm::rcp_nr(e), -M);
+        const double vt = v * tj;
+        ap = a + vt;
+        return fm::exp64_bounded(ap) + fm::exp64_bounded(a - vt);
+    };
+    double S;
+    int cnt = 1;
+    if (-x - M >= -kDrop) {
+        // the window reaches t = 0: grid j h, j >= 0, half weight at 0
+        double ap;
+        S = 0.5 * F(0.0, ap);
+        for (int j = 1; j < kMaxNodes; ++j, ++cnt) {
+            const double tj = j * h;
+            S += F(tj, ap);
+            if (ap < -kDrop && tj > t0)
+                break;
+        }
+    } else {
+        // interior window: grid t0 + j h, walked right then left from t0
+        double ap;
+        S = 0.0;
+        for (int j = 0; j < kMaxNodes; ++j, ++cnt) {
+            S += F(fma(double(j), h, t0), ap);
+            if (ap < -kDrop)
+                break;
+        }
+        for (int j = 1; j < kMaxNodes; ++j, ++cnt) {
+            S += F(fma(double(-j), h, t0), ap);
+            if (ap < -kDrop)
+                break;
+        }
+    }
+    if (nodes != nullptr)
+        *nodes = cnt;
+    return M + fm::log64(0.5 * h * S);
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
 
-// Value of the given branch.  binary32 computes everything in binary32
-// except the two 600-term sums of the integral, accumulated in binary64.
-template <typename T, int KIND>
+// Value of the given branch.  binary32 computes in binary32 except the K
+// fallback, which runs in binary64 for both precisions.  K fallback: the
+// cosh-integral trapezoid for x >= 1e-10; below, the two-term small-argument
+// form (v < 0.3) or the 600-node rule on the u-integral of the paper.
+template <typename T, int KIND, int VAR = VAR_DEFAULT>
 __device__ __forceinline__ T eval_branch(int b, T v, T x) {
+    if (VAR == VAR_SEVEN) {
+        switch (b) {
+        case B7_MU3: return br_mu<T, KIND, 3>(v, x);
+        case B7_MU20: return br_mu<T, KIND, 20>(v, x);
+        case B7_U4: return br_u<T, KIND, 4>(v, x);
+        case B7_U6: return br_u<T, KIND, 6>(v, x);
+        case B7_U9: return br_u<T, KIND, 9>(v, x);
+        case B7_U13: return br_u<T, KIND, 13>(v, x);
+        default: b = BR_FB;
+        }
+    }
     if (b == BR_MU)
-        return br_mu20<T, KIND>(v, x);
+        return br_mu<T, KIND>(v, x);
     if (b == BR_U)
-        return br_u13<T, KIND>(v, x);
+        return br_u<T, KIND>(v, x);
     if (KIND == KIND_I)
         return br_series_i<T>(v, x);
+    constexpr bool u_integral = (VAR == VAR_U_INTEGRAL || VAR == VAR_SIMPSON || VAR == VAR_PAPER);
+    if (!u_integral && x >= T(1e-10))
+        return T(br_k_cosh(double(v), double(x)));
     if (x < T(1e-10) && v < T(0.3))
         return T(br_k_tiny_x(double(v), double(x)));
+    if (VAR == VAR_SIMPSON || VAR == VAR_PAPER)
+        return br_quad_k<T, double, true>(v, x);
     return br_quad_k<T, double>(v, x);
 }
 

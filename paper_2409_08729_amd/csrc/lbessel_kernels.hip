@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <hipcub/hipcub.hpp>
+
 #include "lbessel.h"
 #include "lbessel_serve.h"
 #include "lbessel_device.hpp"
@@ -105,18 +107,18 @@ __device__ __forceinline__ T combine(T v, T x, T g, T p, T y0, T y1) {
 }
 
 // One evaluation that may still hit a special value (the v + 1 order).
-template <typename T, int KIND>
+template <typename T, int KIND, int VAR = VAR_DEFAULT>
 __device__ __forceinline__ T eval_full(T v, T x) {
     T y;
     if (special_value<T, KIND>(v, x, &y))
         return y;
-    return eval_branch<T, KIND>(classify<T, KIND>(v, x), v, x);
+    return eval_branch<T, KIND, VAR>(classify_var<T, KIND, VAR>(v, x), v, x);
 }
 
 // ---------------------------------------------------------------------------
 // Ungrouped kernel: one element per thread, no regrouping.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND, int OP>
+template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= a.n)
@@ -129,8 +131,8 @@ __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
         a.out[i] = res;
         return;
     }
-    const T y0 = eval_full<T, KIND>(v, x);
-    const T y1 = (OpTraits<OP>::nv == 2) ? eval_full<T, KIND>(v + T(1), x) : y0;
+    const T y0 = eval_full<T, KIND, VAR>(v, x);
+    const T y1 = (OpTraits<OP>::nv == 2) ? eval_full<T, KIND, VAR>(v + T(1), x) : y0;
     a.out[i] = combine<T, KIND, OP>(v, x, g, a.p, y0, y1);
 }
 
@@ -157,8 +159,9 @@ __device__ __forceinline__ int rank_below(uint64_t m) {
 }
 
 // One tile (workgroup-wide: every thread of the workgroup must call it).
-template <typename T, int KIND, int OP>
+template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
+    static_assert(VAR != VAR_SEVEN, "the grouped kernel sorts three branches");
     constexpr int NV = OpTraits<OP>::nv;
     constexpr int EPT = TileCfg<NV>::ept;
     constexpr int TILE = TileCfg<NV>::tile;
@@ -190,7 +193,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                 a.out[i] = res;
                 done |= 1u << r;
             } else if (NV == 1) {
-                b0 = classify<T, KIND>(v, x);
+                b0 = classify_var<T, KIND, VAR>(v, x);
             } else {
                 T ys;
                 if (special_value<T, KIND>(v, x, &ys))
@@ -274,7 +277,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             const int b = (j < n_fb) ? BR_FB : (j < n_fb + n_u ? BR_U : BR_MU);
             const T v = order_of<T, KIND, OP>(a, i);
             const T x = a.x[i];
-            const T y = eval_branch<T, KIND>(b, v + T(sub), x);
+            const T y = eval_branch<T, KIND, VAR>(b, v + T(sub), x);
             if (NV == 2) {
                 sm.res[id] = y;
             } else {
@@ -301,9 +304,49 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     }
 }
 
-template <typename T, int KIND, int OP>
+template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 __global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
-    grouped_tile<T, KIND, OP>(a, blockIdx.x);
+    grouped_tile<T, KIND, OP, VAR>(a, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Global sort by branch (the paper's GPU grouping), for measurement: keys
+// from the classifier, a radix sort of (key, index) pairs, then one element
+// per thread in sorted order, gathered by index and scattered back.
+// ---------------------------------------------------------------------------
+template <int KIND, int VAR>
+__global__ __launch_bounds__(kThreads) void k_sort_keys(const double *__restrict__ v,
+                                                        const double *__restrict__ x,
+                                                        uint8_t *__restrict__ key,
+                                                        uint32_t *__restrict__ idx, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const double vv = (KIND == KIND_K) ? fabs(v[i]) : v[i];
+    double y;
+    key[i] = special_value<double, KIND>(vv, x[i], &y) ? uint8_t(7)
+                                                       : uint8_t(classify_var<double, KIND, VAR>(vv, x[i]));
+    idx[i] = uint32_t(i);
+}
+
+template <int KIND, int VAR>
+__global__ __launch_bounds__(kThreads) void k_sorted_eval(const uint8_t *__restrict__ key,
+                                                          const uint32_t *__restrict__ idx,
+                                                          const double *__restrict__ v,
+                                                          const double *__restrict__ x,
+                                                          double *__restrict__ out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t e = idx[i];
+    const double vv = (KIND == KIND_K) ? fabs(v[e]) : v[e];
+    const double xx = x[e];
+    double y;
+    if (key[i] == 7)
+        special_value<double, KIND>(vv, xx, &y);
+    else
+        y = eval_branch<double, KIND, VAR>(int(key[i]), vv, xx);
+    out[e] = y;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,6 +389,27 @@ __global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, u
     T y;
     br[i] = special_value<T, KIND>(vv, x[i], &y) ? uint8_t(BR_NONE)
                                                  : uint8_t(classify<T, KIND>(vv, x[i]));
+}
+
+// Integrand evaluations of the K fallback per element: the node count of the
+// cosh-integral rule, 600 for the u-integral rule (x < 1e-10, v >= 0.3),
+// 0 for every other branch, special value or sub-case.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int32_t *nodes,
+                                                     int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const T vv = fabs(v[i]), xx = x[i];
+    T y;
+    int c = 0;
+    if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB) {
+        if (xx >= T(1e-10))
+            br_k_cosh(double(vv), double(xx), &c);
+        else if (vv >= T(0.3))
+            c = tables::kQuadN;
+    }
+    nodes[i] = c;
 }
 
 template <int KIND>
@@ -586,6 +650,27 @@ int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out, in
                                                     0.5 * p - 1.0, p, s);
 }
 
+int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes, int64_t n,
+                    void *s) {
+    if (n < 0 || (precision != 64 && precision != 32))
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (v == nullptr || x == nullptr || nodes == nullptr)
+        return LBESSEL_EINVAL;
+    uint32_t blocks;
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(s);
+    if (precision == 64)
+        hipLaunchKernelGGL(k_knodes<double>, dim3(blocks), dim3(kThreads), 0, st,
+                           (const double *)v, (const double *)x, nodes, n);
+    else
+        hipLaunchKernelGGL(k_knodes<float>, dim3(blocks), dim3(kThreads), 0, st,
+                           (const float *)v, (const float *)x, nodes, n);
+    return launch_status();
+}
+
 int lbessel_classify(int kind, int precision, const void *v, const void *x, uint8_t *branch,
                      int64_t n, void *s) {
     if (n < 0 || (kind != 0 && kind != 1) || (precision != 64 && precision != 32))
@@ -755,6 +840,105 @@ int64_t lbessel_segment_tiles(int64_t n) {
     if (n < 0)
         return LBESSEL_EINVAL;
     return (n + TileCfg<1>::tile - 1) / TileCfg<1>::tile;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Variants and layouts (measurement)
+// ---------------------------------------------------------------------------
+static int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+static size_t sort_temp_bytes(int64_t n) {
+    size_t temp = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, temp, static_cast<const uint8_t *>(nullptr),
+                                       static_cast<uint8_t *>(nullptr),
+                                       static_cast<const uint32_t *>(nullptr),
+                                       static_cast<uint32_t *>(nullptr), int(n), 0, 3);
+    return temp;
+}
+
+extern "C" int64_t lbessel_eval_variant_workspace(int64_t n) {
+    if (n < 0 || n > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return 0;
+    return 2 * align256(n) + 2 * align256(4 * n) + align256(int64_t(sort_temp_bytes(n)));
+}
+
+template <int KIND, int VAR>
+static int run_variant(int layout, const double *v, const double *x, double *out, int64_t n,
+                       void *work, int64_t work_bytes, hipStream_t st) {
+    Args<double> a{v, x, nullptr, out, n, 0.0, 0.0};
+    uint32_t blocks;
+    if (layout == LBESSEL_LAYOUT_GROUPED) {
+        if (VAR == VAR_SEVEN)
+            return LBESSEL_EINVAL;
+        if (!grid_ok(n, TileCfg<1>::tile, &blocks))
+            return LBESSEL_EINVAL;
+        hipLaunchKernelGGL((k_grouped<double, KIND, OP_LOG, (VAR == VAR_SEVEN ? 0 : VAR)>),
+                           dim3(blocks), dim3(kThreads), 0, st, a);
+        return launch_status();
+    }
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    if (layout == LBESSEL_LAYOUT_NAIVE) {
+        hipLaunchKernelGGL((k_ungrouped<double, KIND, OP_LOG, VAR>), dim3(blocks), dim3(kThreads),
+                           0, st, a);
+        return launch_status();
+    }
+    // LBESSEL_LAYOUT_SORTED
+    const int64_t need = lbessel_eval_variant_workspace(n);
+    if (need < 0 || work == nullptr || work_bytes < need)
+        return LBESSEL_EINVAL;
+    char *w = static_cast<char *>(work);
+    uint8_t *k0 = reinterpret_cast<uint8_t *>(w);
+    uint8_t *k1 = reinterpret_cast<uint8_t *>(w + align256(n));
+    uint32_t *i0 = reinterpret_cast<uint32_t *>(w + 2 * align256(n));
+    uint32_t *i1 = reinterpret_cast<uint32_t *>(w + 2 * align256(n) + align256(4 * n));
+    void *temp = w + 2 * align256(n) + 2 * align256(4 * n);
+    size_t temp_bytes = sort_temp_bytes(n);
+    hipLaunchKernelGGL((k_sort_keys<KIND, VAR>), dim3(blocks), dim3(kThreads), 0, st, v, x, k0,
+                       i0, n);
+    if (hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k0, k1, i0, i1, int(n), 0, 3, st) !=
+        hipSuccess)
+        return LBESSEL_EHIP;
+    hipLaunchKernelGGL((k_sorted_eval<KIND, VAR>), dim3(blocks), dim3(kThreads), 0, st, k1, i1,
+                       v, x, out, n);
+    return launch_status();
+}
+
+template <int KIND>
+static int run_variant_kind(int variant, int layout, const double *v, const double *x,
+                            double *out, int64_t n, void *work, int64_t work_bytes,
+                            hipStream_t st) {
+    switch (variant) {
+    case VAR_DEFAULT: return run_variant<KIND, VAR_DEFAULT>(layout, v, x, out, n, work, work_bytes, st);
+    case VAR_PAPER_REGIMES: return run_variant<KIND, VAR_PAPER_REGIMES>(layout, v, x, out, n, work, work_bytes, st);
+    case VAR_U_INTEGRAL: return run_variant<KIND, VAR_U_INTEGRAL>(layout, v, x, out, n, work, work_bytes, st);
+    case VAR_SIMPSON: return run_variant<KIND, VAR_SIMPSON>(layout, v, x, out, n, work, work_bytes, st);
+    case VAR_PAPER: return run_variant<KIND, VAR_PAPER>(layout, v, x, out, n, work, work_bytes, st);
+    case VAR_SEVEN: return run_variant<KIND, VAR_SEVEN>(layout, v, x, out, n, work, work_bytes, st);
+    default: return LBESSEL_EINVAL;
+    }
+}
+
+extern "C" {
+
+int lbessel_eval_variant(int kind, int variant, int layout, const double *v, const double *x,
+                         double *out, int64_t n, void *work, int64_t work_bytes, void *s) {
+    if ((kind != 0 && kind != 1) || variant < 0 || variant >= VAR_COUNT || layout < 0 ||
+        layout > LBESSEL_LAYOUT_SORTED || n < 0 || n > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    if (layout == LBESSEL_LAYOUT_GROUPED && variant == VAR_SEVEN)
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (v == nullptr || x == nullptr || out == nullptr)
+        return LBESSEL_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(s);
+    return (kind == 0) ? run_variant_kind<KIND_I>(variant, layout, v, x, out, n, work, work_bytes, st)
+                       : run_variant_kind<KIND_K>(variant, layout, v, x, out, n, work, work_bytes, st);
 }
 
 int lbessel_abi_version(void) { return LBESSEL_ABI_VERSION; }
