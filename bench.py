@@ -251,6 +251,39 @@ def ablation_bench(lb, torch, sets, sample=1 << 13):
             "results": res}
 
 
+def order01_bench(lb, torch, n=20_000_000):
+    """Orders 0 and 1 (the paper's v = 0, 1 comparisons): the scalar-order fast
+    path against the general path on the same arguments, x ~ U[0, 150) (the
+    paper's Small region) and x ~ U[150, 1e4) (Large), binary64."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(20240917)
+    res = {}
+    for region, lo, hi in (("small", 0.0, 150.0), ("large", 150.0, 1e4)):
+        x = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64) * (hi - lo) + lo
+        for v in (0.0, 1.0):
+            vv = torch.full_like(x, v)
+            for kind in ("I", "K"):
+                f_fast = lb.log_iv_order if kind == "I" else lb.log_kv_order
+                f_gen = lb.log_iv if kind == "I" else lb.log_kv
+                row = {}
+                for name, call in (("fast", lambda: f_fast(v, x)), ("general", lambda: f_gen(vv, x))):
+                    call()
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(3):
+                        call()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    row[f"{name}_ms"] = e0.elapsed_time(e1) / 3
+                row["speedup"] = row["general_ms"] / row["fast_ms"]
+                row["fast_G_evals_s"] = n / row["fast_ms"] / 1e6
+                res[f"{kind}{int(v)}:{region}"] = row
+        del x, vv
+    return {"n": n, "results": res}
+
+
 def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
     """Open-loop Poisson request stream through the native server: uneven
     evaluation requests (host arrays, 1 .. 4M pairs, I/K, f64/f32) and vMF
@@ -448,6 +481,7 @@ def main():
     ablations = None
     if not args.no_ablation:
         ablations = ablation_bench(lb, torch, sets)
+    order01 = order01_bench(lb, torch)
 
     vmf_res = None
     if not args.no_vmf:
@@ -494,6 +528,7 @@ def main():
         "f32": f32,
         "grouping_ablation": ablation,
         "ablations": ablations,
+        "order01": order01,
         "vmf": vmf_res,
         "serving": serving,
         "kernels": kern,

@@ -79,6 +79,28 @@ int lbessel_log_kv_f64(const double *v, const double *x, double *out,
 int lbessel_log_kv_f32(const float *v, const float *x, float *out,
                        int64_t n, void *stream);
 
+/*
+ * One order for the whole array: out[i] = log I_v(x[i]) / log K_v(x[i]).
+ * v is a host scalar, x and out device arrays of n elements.  Orders 0 and 1
+ * (for K, |v| in {0, 1}) take a fast path whose expansions reduce to
+ * polynomials with constant coefficients (power series of I_0, I_1, DLMF
+ * 10.25.2; small-argument series of K_0, K_1, DLMF 10.31.1; a Chebyshev
+ * expansion of log K_v(x) + x + log(2x/pi)/2 in 1/x on 2 < x <= 17.5; the
+ * Hankel expansion above the thresholds of the general path), the orders of
+ * the paper's v = 0, 1 comparisons (Sec. "Precision", Tables 5 and 7).
+ * Every other order runs the general path with v broadcast, bit-identical to
+ * lbessel_log_{iv,kv}_{f64,f32} on an array filled with v.  Special values
+ * follow the general conventions.
+ */
+int lbessel_log_iv_order_f64(double v, const double *x, double *out, int64_t n,
+                             void *stream);
+int lbessel_log_kv_order_f64(double v, const double *x, double *out, int64_t n,
+                             void *stream);
+int lbessel_log_iv_order_f32(float v, const float *x, float *out, int64_t n,
+                             void *stream);
+int lbessel_log_kv_order_f32(float v, const float *x, float *out, int64_t n,
+                             void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Derivatives in x (the paper names derivatives as future work)            */
 /* ---------------------------------------------------------------------- */

@@ -7,6 +7,7 @@ HIP kernels; there is no CPU path.  If the library is not built, or a tensor
 is not on a GPU, the call raises.
 
 log_iv(v, x), log_kv(v, x)                 log I_v(x), log K_v(x)
+log_iv_order(v, x), log_kv_order(v, x)     one scalar order (fast path for v = 0, 1)
 log_iv_grad_x(v, x, g), log_kv_grad_x(..)  g * d/dx log I_v(x), log K_v(x)
 vmf_log_norm(kappa, p), vmf_log_norm_grad  log C_p(kappa) and d/dkappa
 LogIv, LogKv, VmfLogNorm                   torch.autograd.Function wrappers
@@ -60,6 +61,10 @@ def _load():
         "lbessel_vmf_log_norm_grad_f64": [vp, ctypes.c_double, vp, i64, vp],
         "lbessel_classify": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_k_nodes": [ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_log_iv_order_f64": [ctypes.c_double, vp, vp, i64, vp],
+        "lbessel_log_kv_order_f64": [ctypes.c_double, vp, vp, i64, vp],
+        "lbessel_log_iv_order_f32": [ctypes.c_float, vp, vp, i64, vp],
+        "lbessel_log_kv_order_f32": [ctypes.c_float, vp, vp, i64, vp],
         "lbessel_eval_variant": [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp,
                                  i64, vp],
         "lbessel_eval_branch_f64": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
@@ -139,6 +144,28 @@ def log_iv(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
 def log_kv(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     """log K_v(x), elementwise, float64 or float32."""
     return _unary("lbessel_log_kv", v, x)
+
+
+def _order(name: str, v: float, x: torch.Tensor) -> torch.Tensor:
+    (x,) = _prep(x)
+    out = torch.empty_like(x)
+    fn = f"{name}_{_suffix(x)}"
+    with torch.cuda.device(x.device):
+        _check(getattr(_load(), fn)(float(v), x.data_ptr(), out.data_ptr(), x.numel(),
+                                    _stream(x)), fn)
+    return out
+
+
+def log_iv_order(v: float, x: torch.Tensor) -> torch.Tensor:
+    """log I_v(x) for one order v (host scalar) over the array x; orders 0 and 1
+    take the polynomial fast path."""
+    return _order("lbessel_log_iv_order", v, x)
+
+
+def log_kv_order(v: float, x: torch.Tensor) -> torch.Tensor:
+    """log K_v(x) for one order v (host scalar) over the array x; |v| in {0, 1}
+    takes the polynomial fast path."""
+    return _order("lbessel_log_kv_order", v, x)
 
 
 def _grad(name: str, v, x, g):

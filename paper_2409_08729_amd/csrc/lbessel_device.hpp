@@ -67,6 +67,7 @@ template <> struct Cst<double> {
     static constexpr double half_log_pi = 0x1.250d048e7a1bdp-1;  // log(pi)/2
     static constexpr double log_n = 0x1.99674ba3fdd16p+2;        // log(600)
     static constexpr double ln2 = 0x1.62e42fefa39efp-1;
+    static constexpr double log_pi = 0x1.250d048e7a1bdp+0;         // log(pi)
     static constexpr double series_eps = 0x1p-56;  // relative truncation
     static constexpr double big_z = 1e150;         // sqrt(1+z^2) == z beyond
     static constexpr double tiny_z = 1e-290;       // x/v may have lost bits below
@@ -77,6 +78,7 @@ template <> struct Cst<float> {
     static constexpr float half_log_pi = 0x1.250d04p-1f;
     static constexpr float log_n = 0x1.99674cp+2f;
     static constexpr float ln2 = 0x1.62e430p-1f;
+    static constexpr float log_pi = 0x1.250d04p+0f;
     static constexpr float series_eps = 0x1p-27f;
     static constexpr float big_z = 1e18f;
     static constexpr float tiny_z = 1e-30f;
@@ -483,7 +485,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, int *nodes = nul
             const double iz = fm::rcp_nr(1.0 + z);
             const double psi = fma(0.5 * x, e - r, -v * (1.0 - z) * iz);
             const double dpsi = fma(0.5 * x, e + r, -4.0 * v * v * z * iz * iz);
-            const double dt = psi / dpsi;
+            const double dt = psi * fm::rcp_nr(dpsi);
             t = fmax(t - dt, 0.0);
             if (fabs(dt) < 1e-4)
                 break;
@@ -537,6 +539,103 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, int *nodes = nul
     if (nodes != nullptr)
         *nodes = cnt;
     return M + fm::log64(0.5 * h * S);
+}
+
+// Cost bucket 0..B-1 of a K fallback element: a rough count of the nodes
+// br_k_cosh will visit (window width / step), cut at fixed thresholds.  Only
+// used to order work inside a tile; any value is correct.
+template <int B>
+__device__ __forceinline__ int k_cost_bucket(double v, double x) {
+    static_assert(B == 6, "thresholds are set for six buckets");
+    double w;
+    if (v * v > x) {
+        const double q = v / x;
+        w = fmin(fm::log64(q + sqrt(fma(q, q, 1.0))), 45.0 / v) + 4.0;   // asinh(v/x)
+    } else {
+        const double a = 45.0 / x;
+        w = fm::log64(1.0 + a + sqrt(a * (2.0 + a)));                    // acosh(1 + 45/x)
+    }
+    const double est = w * fma(0.05, v, 1.0) * (1.0 / 0.22);
+    return (est < 19.0) ? 0 : (est < 29.0) ? 1 : (est < 37.0) ? 2 : (est < 45.0) ? 3
+                                                                 : (est < 55.0) ? 4 : 5;
+}
+
+// ---------------------------------------------------------------------------
+// Orders 0 and 1 (scalar-order fast path)
+// ---------------------------------------------------------------------------
+// With v fixed at 0 or 1 every expansion reduces to polynomials with constant
+// coefficients (tables generated in exact or 100-digit arithmetic):
+//   x > x1 (the Hankel region of both orders): br_mu, as on the general path;
+//   I:  log I_v = v log(x/2) + log sum_k q^k/(k!(k+v)!),  q = x^2/4
+//       (DLMF 10.25.2; 48 terms cover x <= 21.5);
+//   K, 2 < x <= x1: log K_v = g_v(1/x) - x - 1/2 log(2x/pi), g_v a degree-20
+//       Chebyshev expansion in s = 1/x on [1/17.5, 1/2] (Clenshaw);
+//   K, x <= 2: DLMF 10.31.1 with n = 0, 1 (18 terms):
+//       K_0 = C(q) - (log(x/2) + gamma) S_0(q),
+//       x K_1 = 1 + q (2 (log(x/2) + gamma) S_1(q) - A(q)),
+//       C_k = H_k/(k!)^2, A_k = (H_k + H_{k+1})/(k!(k+1)!), S_v as for I.
+template <typename T> struct Tab01;
+template <> struct Tab01<double> {
+    static __device__ __forceinline__ const double *iser() { return &tables::kI01Ser64[0][0]; }
+    static __device__ __forceinline__ const double *k0() { return tables::kK0Ser64; }
+    static __device__ __forceinline__ const double *k1() { return tables::kK1Ser64; }
+    static __device__ __forceinline__ const double *cheb() { return &tables::kK01Cheb64[0][0]; }
+    static constexpr double gamma = tables::kEulerGamma64;
+};
+template <> struct Tab01<float> {
+    static __device__ __forceinline__ const float *iser() { return &tables::kI01Ser32[0][0]; }
+    static __device__ __forceinline__ const float *k0() { return tables::kK0Ser32; }
+    static __device__ __forceinline__ const float *k1() { return tables::kK1Ser32; }
+    static __device__ __forceinline__ const float *cheb() { return &tables::kK01Cheb32[0][0]; }
+    static constexpr float gamma = tables::kEulerGamma32;
+};
+
+template <typename T, int NT>
+__device__ __forceinline__ T horner(const LB_CONST_AS T *c, T q) {
+    T s = c[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k)
+        s = fm::fma_c(s, q, c[k]);
+    return s;
+}
+
+template <typename T, int KIND, int V>
+__device__ __forceinline__ T order01(T x) {
+    constexpr RegimeSet r = Regime<T, KIND>::r;
+    if (x > T(r.x1))
+        return br_mu<T, KIND>(T(V), x);
+    const T lx2 = llog(x) - Cst<T>::ln2;                 // log(x/2), safe for subnormal x
+    const T q = T(0.25) * x * x;
+    const LB_CONST_AS T *ser = opaque_const<T>(Tab01<T>::iser()) + V * tables::kI01Terms;
+    if (KIND == KIND_I) {
+        const T s = horner<T, tables::kI01Terms>(ser, q);
+        return (V == 0) ? llog(s) : lx2 + llog(s);
+    }
+    if (x > T(2)) {
+        // Clenshaw on u = (2s - (sa + sb)) / (sb - sa), s = 1/x
+        constexpr T sa = T(1) / T(17.5), sb = T(0.5);
+        const LB_CONST_AS T *c = opaque_const<T>(Tab01<T>::cheb()) + V * (tables::kCheb01Deg + 1);
+        const T u = fma(T(2) / (sb - sa), T(1) / x, -(sa + sb) / (sb - sa));
+        const T u2 = u + u;
+        T b1 = T(0), b2 = T(0);
+#pragma unroll
+        for (int j = tables::kCheb01Deg; j >= 1; --j) {
+            const T b0 = fma(u2, b1, c[j] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        const T g = fma(u, b1, c[0] - b2);
+        return g - x - T(0.5) * (llog(x) + Cst<T>::ln2 - Cst<T>::log_pi);
+    }
+    const T lg = lx2 + Tab01<T>::gamma;
+    if (V == 0) {
+        const T s0 = horner<T, tables::kK01Terms>(ser, q);
+        const T c0 = horner<T, tables::kK01Terms>(opaque_const<T>(Tab01<T>::k0()), q);
+        return llog(c0 - lg * s0);
+    }
+    const T s1 = horner<T, tables::kK01Terms>(ser, q);
+    const T a1 = horner<T, tables::kK01Terms>(opaque_const<T>(Tab01<T>::k1()), q);
+    return llog(fma(q, T(2) * lg * s1 - a1, T(1))) - llog(x);
 }
 
 // ---------------------------------------------------------------------------

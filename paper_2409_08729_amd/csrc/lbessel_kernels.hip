@@ -59,6 +59,8 @@ template <typename T, int KIND, int OP>
 __device__ __forceinline__ T order_of(const Args<T> &a, int64_t i) {
     if (OpTraits<OP>::scalar_order)
         return a.vs;
+    if (a.v == nullptr)   // one order for the whole array (uniform branch)
+        return (KIND == KIND_K) ? fabs(a.vs) : a.vs;
     const T v = a.v[i];
     return (KIND == KIND_K) ? fabs(v) : v;
 }
@@ -145,10 +147,28 @@ template <int NV> struct TileCfg {
     static constexpr int slots = ept * NV;               // evaluations per thread
 };
 
-template <typename T, int NV> struct Smem {
-    uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, branch-sorted
-    int cnt[3][TileCfg<NV>::slots][kWaves];              // counts, then offsets
-    int total[3];
+// Classes an evaluation is sorted into inside a tile: 0 = Hankel, 1 = Debye,
+// 2 + b = fallback bucket b.  The K fallback's cost varies ~10x with (v, x)
+// (its node count), so for the forward K path it is split into kKBuckets
+// buckets by an estimate of that count; lanes of one 64-entry chunk then
+// run loops of similar length.  List order: costliest bucket first, then
+// the cheaper ones, Debye, Hankel.
+constexpr int kKBuckets = 6;
+template <int KIND, int OP, int VAR> struct Classes {
+    static constexpr int fb = (KIND == KIND_K && OpTraits<OP>::nv == 1 &&
+                               (VAR == VAR_DEFAULT || VAR == VAR_PAPER_REGIMES))
+                                  ? kKBuckets
+                                  : 1;
+    static constexpr int n = 2 + fb;
+    static constexpr int bits = (n > 3) ? 4 : 2;
+    static constexpr int none = (1 << bits) - 1;
+};
+
+template <typename T, int NV, int NC> struct Smem {
+    uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, class-sorted
+    int cnt[NC][TileCfg<NV>::slots][kWaves];             // counts, then offsets
+    int start[NC];                                       // first list position per class
+    int n_all;
     int chunk;                                           // next chunk to evaluate
     T res[(NV == 2) ? TileCfg<NV>::tile * 2 : 1];        // log-values of both orders
 };
@@ -166,22 +186,27 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     constexpr int EPT = TileCfg<NV>::ept;
     constexpr int TILE = TileCfg<NV>::tile;
     constexpr int SLOTS = TileCfg<NV>::slots;
-    __shared__ Smem<T, NV> sm;
+    using C = Classes<KIND, OP, VAR>;
+    constexpr int NC = C::n;
+    constexpr int BITS = C::bits;
+    constexpr uint32_t MASK = (1u << BITS) - 1;
+    static_assert(SLOTS * BITS <= 32, "class codes of one thread fit 32 bits");
+    __shared__ Smem<T, NV, NC> sm;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int64_t base = tile * TILE;
 
-    // 1. load, screen, classify.  code: 2 bits per evaluation slot
-    //    (slot = r * NV + sub), BR_NONE = nothing to evaluate.
+    // 1. load, screen, classify.  code: BITS bits per evaluation slot
+    //    (slot = r * NV + sub), C::none = nothing to evaluate.
     uint32_t code = 0;
     uint32_t done = 0;   // bit r: element r finished in this step (or out of range)
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
         const int e = r * kThreads + tid;
         const int64_t i = base + e;
-        int b0 = BR_NONE, b1 = BR_NONE;
+        int b0 = C::none, b1 = C::none;
         if (i >= a.n) {
             done |= 1u << r;
         } else {
@@ -194,6 +219,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                 done |= 1u << r;
             } else if (NV == 1) {
                 b0 = classify_var<T, KIND, VAR>(v, x);
+                if (C::fb > 1 && b0 == BR_FB)
+                    b0 = BR_FB + k_cost_bucket<kKBuckets>(double(v), double(x));
             } else {
                 T ys;
                 if (special_value<T, KIND>(v, x, &ys))
@@ -207,24 +234,24 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                     b1 = classify<T, KIND>(v1, x);
             }
         }
-        code |= uint32_t(b0) << (2 * (r * NV));
+        code |= uint32_t(b0) << (BITS * (r * NV));
         if (NV == 2)
-            code |= uint32_t(b1) << (2 * (r * NV + 1));
+            code |= uint32_t(b1) << (BITS * (r * NV + 1));
     }
 
-    // 2. per-wave counts per (branch, slot), then offsets
+    // 2. per-wave counts per (class, slot), then offsets within each class
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int b = (code >> (2 * s)) & 3;
+        const int b = (code >> (BITS * s)) & MASK;
 #pragma unroll
-        for (int br = 0; br < 3; ++br) {
+        for (int br = 0; br < NC; ++br) {
             const uint64_t m = __ballot(b == br);
             if (lane == 0)
                 sm.cnt[br][s][wave] = __popcll(m);
         }
     }
     __syncthreads();
-    if (tid < 3) {
+    if (tid < NC) {
         const int br = tid;
         int run = 0;
         for (int s = 0; s < SLOTS; ++s)
@@ -233,25 +260,37 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                 sm.cnt[br][s][w] = run;
                 run += c;
             }
-        sm.total[br] = run;
+        sm.start[br] = run;   // class total for now
     }
-    if (tid == 0)
-        sm.chunk = 0;
     __syncthreads();
-    const int n_fb = sm.total[BR_FB];
-    const int n_u = sm.total[BR_U];
-    const int n_all = n_fb + n_u + sm.total[BR_MU];
+    if (tid == 0) {
+        // list order: fallback buckets from costliest down, Debye, Hankel
+        int pos = 0;
+        for (int b = NC - 1; b >= BR_FB; --b) {
+            const int t = sm.start[b];
+            sm.start[b] = pos;
+            pos += t;
+        }
+        const int tu = sm.start[BR_U], tm = sm.start[BR_MU];
+        sm.start[BR_U] = pos;
+        sm.start[BR_MU] = pos + tu;
+        sm.n_all = pos + tu + tm;
+        sm.chunk = 0;
+    }
+    __syncthreads();
+    const int n_fb = sm.start[BR_U];              // all fallback buckets
+    const int n_fb_u = sm.start[BR_MU];           // ... plus Debye
+    const int n_all = sm.n_all;
 
-    // 3. scatter evaluation ids: [fallback | Debye | Hankel]
+    // 3. scatter evaluation ids in list order
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int b = (code >> (2 * s)) & 3;
+        const int b = (code >> (BITS * s)) & MASK;
 #pragma unroll
-        for (int br = 0; br < 3; ++br) {
+        for (int br = 0; br < NC; ++br) {
             const uint64_t m = __ballot(b == br);
             if (b == br) {
-                const int start = (br == BR_FB) ? 0 : (br == BR_U ? n_fb : n_fb + n_u);
-                const int pos = start + sm.cnt[br][s][wave] + rank_below(m);
+                const int pos = sm.start[br] + sm.cnt[br][s][wave] + rank_below(m);
                 const int r = s / NV, sub = s - (s / NV) * NV;
                 sm.list[pos] = uint16_t((r * kThreads + tid) * NV + sub);
             }
@@ -274,7 +313,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             const int e = id / NV;
             const int sub = id - e * NV;
             const int64_t i = base + e;
-            const int b = (j < n_fb) ? BR_FB : (j < n_fb + n_u ? BR_U : BR_MU);
+            const int b = (j < n_fb) ? BR_FB : (j < n_fb_u ? BR_U : BR_MU);
             const T v = order_of<T, KIND, OP>(a, i);
             const T x = a.x[i];
             const T y = eval_branch<T, KIND, VAR>(b, v + T(sub), x);
@@ -374,6 +413,22 @@ __global__ __launch_bounds__(kThreads) void k_grouped_seg(
     Args<T> a{static_cast<const T *>(sg.v), static_cast<const T *>(sg.x), nullptr,
               static_cast<T *>(sg.out), sg.n, T(0), T(0)};
     grouped_tile<T, KIND, OP_LOG>(a, t - sg.tile0);
+}
+
+// ---------------------------------------------------------------------------
+// Orders 0 and 1: one element per thread, polynomial evaluations only
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, int V>
+__global__ __launch_bounds__(kThreads) void k_order01(const T *__restrict__ x,
+                                                      T *__restrict__ out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const T xx = x[i];
+    T y;
+    if (!special_value<T, KIND>(T(V), xx, &y))
+        y = order01<T, KIND, V>(xx);
+    out[i] = y;
 }
 
 // ---------------------------------------------------------------------------
@@ -648,6 +703,53 @@ int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out, in
         return LBESSEL_EINVAL;
     return run_grouped<double, KIND_I, OP_VMF_GRAD>(nullptr, kappa, nullptr, out, n,
                                                     0.5 * p - 1.0, p, s);
+}
+
+}  // extern "C"
+
+// Scalar order: orders 0 and 1 take the polynomial kernel, every other order
+// the grouped kernel with the order broadcast.
+template <typename T, int KIND>
+static int run_order(T v, const T *x, T *out, int64_t n, hipStream_t st) {
+    if (n < 0)
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (x == nullptr || out == nullptr)
+        return LBESSEL_EINVAL;
+    const T av = (KIND == KIND_K) ? fabs(v) : v;
+    uint32_t blocks;
+    if (av == T(0) || av == T(1)) {
+        if (!grid_ok(n, kThreads, &blocks))
+            return LBESSEL_EINVAL;
+        if (av == T(0))
+            hipLaunchKernelGGL((k_order01<T, KIND, 0>), dim3(blocks), dim3(kThreads), 0, st, x,
+                               out, n);
+        else
+            hipLaunchKernelGGL((k_order01<T, KIND, 1>), dim3(blocks), dim3(kThreads), 0, st, x,
+                               out, n);
+        return launch_status();
+    }
+    if (!grid_ok(n, TileCfg<1>::tile, &blocks))
+        return LBESSEL_EINVAL;
+    Args<T> a{nullptr, x, nullptr, out, n, v, T(0)};
+    hipLaunchKernelGGL((k_grouped<T, KIND, OP_LOG>), dim3(blocks), dim3(kThreads), 0, st, a);
+    return launch_status();
+}
+
+extern "C" {
+
+int lbessel_log_iv_order_f64(double v, const double *x, double *out, int64_t n, void *s) {
+    return run_order<double, KIND_I>(v, x, out, n, static_cast<hipStream_t>(s));
+}
+int lbessel_log_kv_order_f64(double v, const double *x, double *out, int64_t n, void *s) {
+    return run_order<double, KIND_K>(v, x, out, n, static_cast<hipStream_t>(s));
+}
+int lbessel_log_iv_order_f32(float v, const float *x, float *out, int64_t n, void *s) {
+    return run_order<float, KIND_I>(v, x, out, n, static_cast<hipStream_t>(s));
+}
+int lbessel_log_kv_order_f32(float v, const float *x, float *out, int64_t n, void *s) {
+    return run_order<float, KIND_K>(v, x, out, n, static_cast<hipStream_t>(s));
 }
 
 int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes, int64_t n,

@@ -14,6 +14,14 @@ nearest, into binary64 and binary32 hex literals:
   correction is needed at u = 0, where both integrands vanish to high order
   (g ~ u^7, h ~ exp(-1/u)).  The paper's Simpson weights are emitted as well.
 * Per-node constants log u_j and 1/u_j.
+* Orders 0 and 1 (the scalar-order fast path):
+  - the power series of I_0, I_1 (DLMF 10.25.2): 1/(k! (k+v)!), k < 48;
+  - the small-argument series of K_0, K_1 (DLMF 10.31.1 with n = 0, 1,
+    psi(k+1) = H_k - gamma): H_k/(k!)^2 and (H_k + H_{k+1} - 2 gamma)/(k!(k+1)!);
+  - Chebyshev coefficients of g_v(s) = log K_v(1/s) + 1/s + 1/2 log(2/(pi s))
+    on s = 1/x in [1/17.5, 1/2], from K_0, K_1 evaluated by the same series
+    in 100-digit decimal arithmetic at the Chebyshev points (the series
+    cancels there by up to ~1e15, far below that precision).
 
 Run as a script it writes ``csrc/lbessel_tables.h``.
 """
@@ -164,6 +172,105 @@ def f32_hex(x: float) -> str:
     return float(x).hex() + "f"
 
 
+# ----------------------------------------------------------------------------
+# Orders 0 and 1
+# ----------------------------------------------------------------------------
+I01_TERMS = 48       # I_0, I_1 series terms (x <= 21.5: tail < 2^-60)
+K01_TERMS = 18       # K_0, K_1 small-argument series terms (x <= 2)
+CHEB01_DEG = 20      # Chebyshev degree of g_v on x in [2, 17.5]
+CHEB01_X = (Fraction(2), Fraction(35, 2))
+PI_50 = "3.14159265358979323846264338327950288419716939937510582097494459"
+EULER_GAMMA_50 = "0.57721566490153286060651209008240243104215933593992359880576723"
+
+
+def i01_series(v: int) -> list[Fraction]:
+    return [Fraction(1, math.factorial(k) * math.factorial(k + v)) for k in range(I01_TERMS)]
+
+
+def _harmonic(k: int) -> Fraction:
+    return sum((Fraction(1, j) for j in range(1, k + 1)), Fraction(0))
+
+
+def k0_series() -> list[Fraction]:
+    """H_k / (k!)^2: K_0(x) = sum_k H_k q^k/(k!)^2 - (log(x/2) + gamma) I_0(x), q = x^2/4."""
+    return [_harmonic(k) / math.factorial(k) ** 2 for k in range(K01_TERMS)]
+
+
+def k1_series():
+    """(H_k + H_{k+1})/(k!(k+1)!) and 1/(k!(k+1)!) (the -2 gamma part):
+    x K_1(x) = 1 + 2 q log(x/2) S_1(q) - q sum_k (H_k + H_{k+1} - 2 gamma) q^k/(k!(k+1)!)."""
+    a = [(_harmonic(k) + _harmonic(k + 1)) / (math.factorial(k) * math.factorial(k + 1))
+         for k in range(K01_TERMS)]
+    b = [Fraction(1, math.factorial(k) * math.factorial(k + 1)) for k in range(K01_TERMS)]
+    return a, b
+
+
+def _dec_cos(z, prec):
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec + 10
+        z = Decimal(z)
+        two_pi = 2 * Decimal(PI_50)
+        z = z - two_pi * (z / two_pi).to_integral_value()     # |z| <= pi
+        term, acc, k = Decimal(1), Decimal(1), 0
+        while abs(term) > Decimal(10) ** -(prec + 5):
+            k += 2
+            term = -term * z * z / (k * (k - 1))
+            acc += term
+        return +acc
+
+
+def k01_decimal(v: int, x, prec: int = 100):
+    """K_v(x), v in {0, 1}, by the DLMF 10.31.1 series in `prec`-digit decimals."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec
+        x = Decimal(x)
+        g = Decimal(EULER_GAMMA_50)
+        q = x * x / 4
+        l2 = (x / 2).ln()
+        s_i = s_k = Decimal(0)
+        term = Decimal(1) if v == 0 else Decimal(1)
+        h, h1 = Decimal(0), Decimal(1)          # H_k, H_{k+1}
+        k = 0
+        while True:
+            s_i += term
+            s_k += (h if v == 0 else h + h1 - 2 * g) * term
+            if k > 8 and term < Decimal(10) ** -(prec - 5) * s_i:
+                break
+            k += 1
+            h += Decimal(1) / k
+            h1 += Decimal(1) / (k + 1)
+            term = term * q / (k * (k + v))
+        if v == 0:
+            return s_k - (l2 + g) * s_i
+        return 1 / x + l2 * (x / 2) * s_i - x / 4 * s_k
+
+
+def k01_chebyshev(v: int, deg: int = CHEB01_DEG, prec: int = 100):
+    """Chebyshev coefficients c_0..c_deg of g_v(s) = log K_v(x) + x + 1/2 log(2x/pi),
+    s = 1/x on [1/17.5, 1/2], mapped to u in [-1, 1] (u = -1 at x = 17.5)."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec
+        pi = Decimal(PI_50)
+        sa = Decimal(1) / Decimal(float(CHEB01_X[1]))
+        sb = Decimal(1) / Decimal(float(CHEB01_X[0]))
+        n = deg + 1
+        th = [pi * (Decimal(k) + Decimal("0.5")) / n for k in range(n)]
+        us = [_dec_cos(t, prec) for t in th]
+        gs = []
+        for u in us:
+            s_ = (sa + sb) / 2 + (sb - sa) / 2 * u
+            x = 1 / s_
+            gs.append(k01_decimal(v, x, prec).ln() + x + (2 * x / pi).ln() / 2)
+        cs = []
+        for j in range(n):
+            c = sum(gs[k] * _dec_cos(j * th[k], prec) for k in range(n)) * 2 / n
+            cs.append(c / 2 if j == 0 else c)
+        return cs
+
+
 def _debye_arrays():
     polys = debye_polys(U_TERMS)
     rows = [debye_p_coeffs(k, polys) for k in range(1, U_TERMS + 1)]
@@ -226,6 +333,40 @@ def render_header() -> str:
             lines.append("    {" + ", ".join((fmt(conv_q(u)), fmt(conv_d(lu)), fmt(conv_q(iu))))
                          + "},")
         lines.append("};")
+    # orders 0 and 1
+    lines.append("")
+    lines.append(f"constexpr int kI01Terms = {I01_TERMS};")
+    lines.append(f"constexpr int kK01Terms = {K01_TERMS};")
+    lines.append(f"constexpr int kCheb01Deg = {CHEB01_DEG};")
+    lines.append("// I_v series coefficients 1/(k!(k+v)!), v = 0, 1.")
+    for name, conv, fmt, ty in (("kI01Ser64", to_f64, f64_hex, "double"),
+                                ("kI01Ser32", to_f32_exact, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[2][{I01_TERMS}] = {{")
+        for v in (0, 1):
+            lines.append("    {" + ", ".join(fmt(conv(c)) for c in i01_series(v)) + "},")
+        lines.append("};")
+    k1a, k1b = k1_series()
+    lines.append("// K_0: H_k/(k!)^2; K_1: (H_k + H_{k+1})/(k!(k+1)!).")
+    for name, conv, fmt, ty in (("kK0Ser64", to_f64, f64_hex, "double"),
+                                ("kK0Ser32", to_f32_exact, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[{K01_TERMS}] = {{"
+                     + ", ".join(fmt(conv(c)) for c in k0_series()) + "};")
+    for name, conv, fmt, ty in (("kK1Ser64", to_f64, f64_hex, "double"),
+                                ("kK1Ser32", to_f32_exact, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[{K01_TERMS}] = {{"
+                     + ", ".join(fmt(conv(c)) for c in k1a) + "};")
+    lines.append("// Chebyshev coefficients of log K_v(x) + x + 1/2 log(2x/pi) in s = 1/x,")
+    lines.append("// s in [1/17.5, 1/2] mapped to u in [-1, 1]; rows v = 0, 1.")
+    cheb = [k01_chebyshev(0), k01_chebyshev(1)]
+    for name, conv, fmt, ty in (("kK01Cheb64", dec_to_f64, f64_hex, "double"),
+                                ("kK01Cheb32", dec_to_f32, f32_hex, "float")):
+        lines.append(f"__constant__ const {ty} {name}[2][{CHEB01_DEG + 1}] = {{")
+        for row in cheb:
+            lines.append("    {" + ", ".join(fmt(conv(c)) for c in row) + "},")
+        lines.append("};")
+    from decimal import Decimal
+    lines.append(f"constexpr double kEulerGamma64 = {f64_hex(dec_to_f64(Decimal(EULER_GAMMA_50)))};")
+    lines.append(f"constexpr float kEulerGamma32 = {f32_hex(dec_to_f32(Decimal(EULER_GAMMA_50)))};")
     lines.append("")
     lines.append("}  // namespace tables")
     lines.append("}  // namespace lbessel")

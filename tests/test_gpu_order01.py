@@ -1,0 +1,105 @@
+"""Scalar-order entry points: orders 0 and 1 take the polynomial fast path
+(checked against the binary128 oracle, f64 and f32, over the whole argument
+range and across every internal boundary); any other order runs the general
+path with v broadcast and must give the array path's bits."""
+import numpy as np
+import pytest
+import torch
+
+from parity import TOL32, TOL64, cond_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the -m gpu tests need an MI355X")
+    import paper_2409_08729_amd as m
+    m.lib()
+    return m
+
+
+def _xgrid(seed=0):
+    g = np.random.default_rng(seed)
+    parts = [10 ** g.uniform(-300, -10, 300), 10 ** g.uniform(-10, np.log10(2.0), 3000),
+             g.uniform(2.0, 22.0, 3000), 10 ** g.uniform(np.log10(22.0), 4, 2000)]
+    edges = []
+    for b in (2.0, 7.5, 9.5, 17.5, 21.5):
+        edges += [np.nextafter(b, 0), b, np.nextafter(b, 100), b * (1 - 1e-9), b * (1 + 1e-9)]
+    # the oracle covers x <= 1e12 (I) and 1e15 (K); larger x is checked against
+    # the leading Hankel term in test_order_fast_path_huge_x
+    return np.concatenate(parts + [np.array(edges), np.array([5e-324, 2.2e-308, 1e11])])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("v", [0.0, 1.0])
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_orders_0_and_1_match_oracle(lb, oracle, kind, v, dtype):
+    x = _xgrid()
+    if kind == "I":
+        x = x[x <= 700.0] if dtype == torch.float32 else x
+    if dtype == torch.float32:
+        x = x.astype(np.float32)
+        x = x[(x > 0) & np.isfinite(x)]
+    dx = torch.from_numpy(x).to("cuda:0")
+    y = (lb.log_iv_order if kind == "I" else lb.log_kv_order)(v, dx).cpu().numpy()
+    xd = x.astype(np.float64)
+    hi, lo = (oracle.log_iv if kind == "I" else oracle.log_kv)(np.full(xd.size, v), xd)
+    fin = np.isfinite(hi)
+    assert np.array_equal(np.isfinite(y), fin)
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    e = cond_err(y.astype(np.float64)[fin], hi[fin], lo[fin], np.full(fin.sum(), v), xd[fin])
+    i = int(np.argmax(e))
+    assert e.max() <= tol, (kind, v, dtype, e.max(), xd[fin][i])
+
+
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_order_fast_path_specials(lb, kind):
+    x = torch.tensor([0.0, np.inf, np.nan, -1.0], dtype=torch.float64, device="cuda:0")
+    for v in (0.0, 1.0):
+        y = (lb.log_iv_order if kind == "I" else lb.log_kv_order)(v, x).cpu().numpy()
+        ref = (lb.log_iv if kind == "I" else lb.log_kv)(torch.full_like(x, v), x).cpu().numpy()
+        assert np.array_equal(np.isnan(y), np.isnan(ref)) and np.array_equal(
+            np.nan_to_num(y), np.nan_to_num(ref)), (kind, v, y, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_other_orders_equal_array_path_bitwise(lb, kind, dtype):
+    x = torch.from_numpy(_xgrid(1)).to("cuda:0", dtype)
+    f_ord = lb.log_iv_order if kind == "I" else lb.log_kv_order
+    f_arr = lb.log_iv if kind == "I" else lb.log_kv
+    it = torch.int64 if dtype == torch.float64 else torch.int32
+    for v in (0.5, 2.0, 7.25, 30.0, 1e3):
+        a = f_ord(v, x)
+        b = f_arr(torch.full_like(x, v), x)
+        assert torch.equal(a.view(it), b.view(it)), (kind, v)
+
+
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_fast_path_hankel_region_equals_general_path(lb, kind):
+    # above the Hankel threshold both paths run the same mu_20 code
+    x = torch.linspace(22.0, 5000.0, 10007, dtype=torch.float64, device="cuda:0")
+    for v in (0.0, 1.0):
+        a = (lb.log_iv_order if kind == "I" else lb.log_kv_order)(v, x)
+        b = (lb.log_iv if kind == "I" else lb.log_kv)(torch.full_like(x, v), x)
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+
+
+def test_k_order_is_even(lb):
+    x = torch.from_numpy(_xgrid(2)).to("cuda:0")
+    for v in (1.0, 3.5):
+        assert torch.equal(lb.log_kv_order(-v, x).view(torch.int64),
+                           lb.log_kv_order(v, x).view(torch.int64))
+
+
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_order_fast_path_huge_x(lb, kind):
+    x = np.array([1e15, 1e100, 1e200, 1e308])
+    for v in (0.0, 1.0):
+        y = (lb.log_iv_order if kind == "I" else lb.log_kv_order)(
+            v, torch.from_numpy(x).cuda()).cpu().numpy()
+        lead = (x - 0.5 * (np.log(2 * np.pi) + np.log(x)) if kind == "I"
+                else 0.5 * (np.log(np.pi / 2) - np.log(x)) - x)
+        assert np.all(np.abs(y - lead) <= 4e-15 * np.abs(lead) + 1e-14), (kind, v, y, lead)

@@ -99,3 +99,59 @@ def test_rounding_helpers():
     assert gt.to_f32_exact(Fraction(-5, 24)) == float(np.float32(-5 / 24))
     lu = gt.node_constants(600)[0][1]
     assert gt.dec_to_f64(lu) == math.log(1 / 600) or abs(gt.dec_to_f64(lu) - math.log(1 / 600)) <= 1e-15
+
+
+# ----------------------------------------------------------------------------
+# Orders 0 and 1 (scalar-order fast path tables)
+# ----------------------------------------------------------------------------
+
+def test_constant_literals():
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 60
+        assert abs(Decimal(gt.PI_50) - cf.pi_dec(60)) < Decimal("1e-58")
+        assert abs(Decimal(gt.EULER_GAMMA_50) - cf.euler_gamma(60)) < Decimal("1e-58")
+
+
+def test_k01_decimal_series_matches_oracle(oracle):
+    from decimal import Decimal
+    xs = [1e-5, 0.3, 1.0, 2.0, 5.5, 11.0, 17.5]
+    for v in (0, 1):
+        hi, lo = oracle.log_kv(np.full(len(xs), float(v)), np.array(xs))
+        for x, h, l in zip(xs, hi, lo):
+            got = gt.k01_decimal(v, x, 80).ln()
+            assert abs(got - (Decimal(h) + Decimal(l))) < Decimal("1e-28") * Decimal(max(1.0, abs(h))), (v, x)
+
+
+def test_k01_chebyshev_reconstructs_g():
+    # the emitted binary64 coefficients reproduce g_v(1/x) to ~1e-17 on [2, 17.5]
+    from decimal import Decimal
+    import math as m
+    g = np.random.default_rng(4)
+    sa, sb = 1 / 17.5, 0.5
+    for v in (0, 1):
+        c = [float(Fraction(d)) for d in gt.k01_chebyshev(v)]
+        for x in g.uniform(2.0, 17.5, 12):
+            u = (2 / x - (sa + sb)) / (sb - sa)
+            t = [1.0, u]
+            while len(t) < len(c):
+                t.append(2 * u * t[-1] - t[-2])
+            approx = sum(ci * ti for ci, ti in zip(c, t))
+            ref = float(gt.k01_decimal(v, x, 60).ln() + Decimal(x)
+                        + (2 * Decimal(x) / Decimal(gt.PI_50)).ln() / 2)
+            assert abs(approx - ref) < 5e-17, (v, x, approx - ref)
+
+
+def test_order01_series_tables():
+    s0 = gt.i01_series(0)
+    s1 = gt.i01_series(1)
+    assert s0[3] == Fraction(1, 36) and s1[3] == Fraction(1, 144)
+    c = gt.k0_series()
+    assert c[0] == 0 and c[2] == Fraction(3, 2) / 4
+    a, b = gt.k1_series()
+    assert a[0] == 1 and b[1] == Fraction(1, 2) and a[1] == Fraction(1 + Fraction(3, 2), 2)
+    # I_0 tail beyond the table at x = 21.5 is negligible
+    q = Fraction(43, 4) ** 2
+    head = sum(cc * q ** k for k, cc in enumerate(s0))
+    nxt = q ** len(s0) / math.factorial(len(s0)) ** 2
+    assert nxt / head < Fraction(1, 2 ** 60)
