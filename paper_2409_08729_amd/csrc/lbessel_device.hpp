@@ -468,8 +468,27 @@ __device__ __forceinline__ double br_k_tiny_x(double v, double x) {
 // are multiples of 1/64, so every t_j is exact and the only rounding in a
 // term is that of its own exponent.  The sum is kept relative to the
 // log-integrand at the grid point nearest t* (log-sum shift).
+// e^t at the grid nodes of br_k_cosh (t = i/64, 0 <= i < 4096) as e^{i>>6} e^{(i&63)/64},
+// indices clamped to the tables (a node beyond t = 64 only ever ends a walk);
+// two correctly rounded table entries and one product (<= 1.5 ulp).  The
+// tables are copied into LDS by the kernel (ktab_load) before any use.
+struct KTab {
+    double eint[64];
+    double efrac[64];
+};
+
+// Cooperative copy of the tables into LDS; every thread of the workgroup
+// must call it, before any evaluation of the K fallback.
+__device__ __forceinline__ void ktab_load(KTab *t) {
+    for (int i = threadIdx.x; i < 128; i += blockDim.x)
+        (i < 64 ? t->eint[i] : t->efrac[i - 64]) =
+            (i < 64) ? tables::kExpInt64[i] : tables::kExpFrac64[i - 64];
+    __syncthreads();
+}
+
 // nodes (may be null): receives the number of integrand evaluations.
-__device__ __forceinline__ double br_k_cosh(double v, double x, int *nodes = nullptr) {
+__device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
+                                            int *nodes = nullptr) {
     constexpr double kGrid = 1.0 / 64.0;
     constexpr double kDrop = 45.0;          // e^-45 ~ 3e-20 of the peak term
     constexpr int kMaxNodes = 1024;         // every walk ends (window <= ~40 / h)
@@ -493,48 +512,53 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, int *nodes = nul
     }
     const double et = fm::exp64(t);
     const double ch = 0.5 * (et + fm::rcp_nr(et));
-    double h = fmin(0.22 / fma(0.05, v, 1.0), 0.5 / sqrt(x * ch));
-    h = fmax(floor(h * 64.0), 1.0) * kGrid;
-    const double t0 = rint(t * 64.0) * kGrid;
+    const int hq = max(int(floor(fmin(0.22 / fma(0.05, v, 1.0), 0.5 / sqrt(x * ch)) * 64.0)), 1);
+    const int t0q = int(rint(t * 64.0));
+    const double h = hq * kGrid;
+    const double t0 = t0q * kGrid;
     // shift M = log-integrand at t0 (log cosh(vt) = vt + log1p(e^{-2vt}) - ln 2)
     const double e0 = fm::exp64(t0);
     const double vt0 = v * t0;
     const double M = fma(-0.5 * x, e0 + fm::rcp_nr(e0), vt0) +
                      fm::log64(1.0 + fm::exp64(-2.0 * vt0)) - Cst<double>::ln2;
-    // F(t) = 2 exp(-x cosh t - M) cosh(v t); ap = -x cosh t + v t - M
-    auto F = [&](double tj, double &ap) -> double {
-        const double e = fm::exp64_bounded(tj);
-        const double a = fma(-0.5 * x, e + fm::rcp_nr(e), -M);
-        const double vt = v * tj;
-        ap = a + vt;
-        return fm::exp64_bounded(ap) + fm::exp64_bounded(a - vt);
+    // One walk over nodes i = i0 + j*di (units of 1/64), j = j0, j0+1, ...:
+    // F(t) = E+ + E-, E+ = exp(-x cosh t + v t - M), E- = E+ r with
+    // r = e^{-2 v t} carried by a product with e^{-2 v di/64}, recomputed
+    // every 16 nodes (its relative error stays below 16 ulp, and it only
+    // enters through E-).  Stops after the first node with log E+ < -kDrop
+    // (and, for a walk from 0, past t0).
+    auto walk = [&](int i0, int di, int j0, double w0, bool past_t0, int &cnt) -> double {
+        const double q2 = fm::exp64_bounded(-2.0 * v * (di * kGrid));
+        double S = 0.0, r = 1.0;
+        for (int j = j0; j < j0 + kMaxNodes; ++j) {
+            const int iq = i0 + j * di;
+            const double tj = iq * kGrid;
+            if (((j - j0) & 15) == 0)
+                r = fm::exp64_bounded(-2.0 * v * tj);
+            // e^{|t|}: a walk from t0 may step past t = 0, where the even
+            // integrand is evaluated at its mirror node
+            const int aq = abs(iq);
+            const double e = kt->eint[min(aq >> 6, 63)] * kt->efrac[aq & 63];
+            const double a = fma(-0.5 * x, e + fm::rcp_nr(e), -M);
+            const double ap = fma(v, tj, a);
+            const double ep = fm::exp64_bounded(ap);
+            const double f = fma(ep, r, ep);
+            S = (j == j0) ? fma(w0, f, S) : S + f;
+            r *= q2;
+            ++cnt;
+            if (ap < -kDrop && (!past_t0 || iq > t0q))
+                break;
+        }
+        return S;
     };
     double S;
-    int cnt = 1;
+    int cnt = 0;
     if (-x - M >= -kDrop) {
         // the window reaches t = 0: grid j h, j >= 0, half weight at 0
-        double ap;
-        S = 0.5 * F(0.0, ap);
-        for (int j = 1; j < kMaxNodes; ++j, ++cnt) {
-            const double tj = j * h;
-            S += F(tj, ap);
-            if (ap < -kDrop && tj > t0)
-                break;
-        }
+        S = walk(0, hq, 0, 0.5, true, cnt);
     } else {
         // interior window: grid t0 + j h, walked right then left from t0
-        double ap;
-        S = 0.0;
-        for (int j = 0; j < kMaxNodes; ++j, ++cnt) {
-            S += F(fma(double(j), h, t0), ap);
-            if (ap < -kDrop)
-                break;
-        }
-        for (int j = 1; j < kMaxNodes; ++j, ++cnt) {
-            S += F(fma(double(-j), h, t0), ap);
-            if (ap < -kDrop)
-                break;
-        }
+        S = walk(t0q, hq, 0, 1.0, false, cnt) + walk(t0q, -hq, 1, 1.0, false, cnt);
     }
     if (nodes != nullptr)
         *nodes = cnt;
@@ -647,7 +671,7 @@ __device__ __forceinline__ T order01(T x) {
 // cosh-integral trapezoid for x >= 1e-10; below, the two-term small-argument
 // form (v < 0.3) or the 600-node rule on the u-integral of the paper.
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
-__device__ __forceinline__ T eval_branch(int b, T v, T x) {
+__device__ __forceinline__ T eval_branch(int b, T v, T x, const KTab *kt) {
     if (VAR == VAR_SEVEN) {
         switch (b) {
         case B7_MU3: return br_mu<T, KIND, 3>(v, x);
@@ -667,7 +691,7 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x) {
         return br_series_i<T>(v, x);
     constexpr bool u_integral = (VAR == VAR_U_INTEGRAL || VAR == VAR_SIMPSON || VAR == VAR_PAPER);
     if (!u_integral && x >= T(1e-10))
-        return T(br_k_cosh(double(v), double(x)));
+        return T(br_k_cosh(double(v), double(x), kt));
     if (x < T(1e-10) && v < T(0.3))
         return T(br_k_tiny_x(double(v), double(x)));
     if (VAR == VAR_SIMPSON || VAR == VAR_PAPER)
@@ -675,15 +699,6 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x) {
     return br_quad_k<T, double>(v, x);
 }
 
-// Full scalar evaluation (special values, branch choice, branch).
-template <typename T, int KIND>
-__device__ __forceinline__ T eval_scalar(T v, T x) {
-    if (KIND == KIND_K)
-        v = fabs(v);
-    T y;
-    if (special_value<T, KIND>(v, x, &y))
-        return y;
-    return eval_branch<T, KIND>(classify<T, KIND>(v, x), v, x);
-}
+
 
 }  // namespace lbessel

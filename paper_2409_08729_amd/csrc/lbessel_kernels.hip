@@ -110,11 +110,21 @@ __device__ __forceinline__ T combine(T v, T x, T g, T p, T y0, T y1) {
 
 // One evaluation that may still hit a special value (the v + 1 order).
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
-__device__ __forceinline__ T eval_full(T v, T x) {
+__device__ __forceinline__ T eval_full(T v, T x, const KTab *kt) {
     T y;
     if (special_value<T, KIND>(v, x, &y))
         return y;
-    return eval_branch<T, KIND, VAR>(classify_var<T, KIND, VAR>(v, x), v, x);
+    return eval_branch<T, KIND, VAR>(classify_var<T, KIND, VAR>(v, x), v, x, kt);
+}
+
+// LDS copy of the K fallback's exp tables, loaded by every workgroup of a K
+// kernel before its first evaluation (all threads must reach the call).
+template <int KIND>
+__device__ __forceinline__ const KTab *ktab_for_kind() {
+    __shared__ KTab kt;
+    if (KIND == KIND_K)
+        ktab_load(&kt);
+    return &kt;
 }
 
 // ---------------------------------------------------------------------------
@@ -122,6 +132,7 @@ __device__ __forceinline__ T eval_full(T v, T x) {
 // ---------------------------------------------------------------------------
 template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
+    const KTab *kt = ktab_for_kind<KIND>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= a.n)
         return;
@@ -133,8 +144,8 @@ __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
         a.out[i] = res;
         return;
     }
-    const T y0 = eval_full<T, KIND, VAR>(v, x);
-    const T y1 = (OpTraits<OP>::nv == 2) ? eval_full<T, KIND, VAR>(v + T(1), x) : y0;
+    const T y0 = eval_full<T, KIND, VAR>(v, x, kt);
+    const T y1 = (OpTraits<OP>::nv == 2) ? eval_full<T, KIND, VAR>(v + T(1), x, kt) : y0;
     a.out[i] = combine<T, KIND, OP>(v, x, g, a.p, y0, y1);
 }
 
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
 // Grouped kernel
 // ---------------------------------------------------------------------------
 template <int NV> struct TileCfg {
-    static constexpr int ept = (NV == 1) ? 8 : 4;        // elements per thread
+    static constexpr int ept = 4;                        // elements per thread
     static constexpr int tile = kThreads * ept;          // elements per tile
     static constexpr int slots = ept * NV;               // evaluations per thread
 };
@@ -164,11 +175,20 @@ template <int KIND, int OP, int VAR> struct Classes {
     static constexpr int none = (1 << bits) - 1;
 };
 
-template <typename T, int NV, int NC> struct Smem {
+// K forward (STAGE): the tile's (order, argument) pairs are staged in LDS in
+// step 1 and the results in the order slots in step 4, so HBM sees one
+// coalesced read of (v, x) and one coalesced write of the results per
+// element, however long the tile's integrals take.  Other operations finish
+// a tile quickly enough that the step-4 re-reads hit L2, and they skip the
+// extra LDS traffic.
+template <typename T, int NV, int NC, bool STAGE> struct Smem {
+    T sv[STAGE ? TileCfg<NV>::tile : 1];                 // order, then result
+    T sx[STAGE ? TileCfg<NV>::tile : 1];                 // argument
     uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, class-sorted
     int cnt[NC][TileCfg<NV>::slots][kWaves];             // counts, then offsets
     int start[NC];                                       // first list position per class
     int n_all;
+    int uniform;                                         // the only class present, or -1
     int chunk;                                           // next chunk to evaluate
     T res[(NV == 2) ? TileCfg<NV>::tile * 2 : 1];        // log-values of both orders
 };
@@ -191,8 +211,10 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     constexpr int BITS = C::bits;
     constexpr uint32_t MASK = (1u << BITS) - 1;
     static_assert(SLOTS * BITS <= 32, "class codes of one thread fit 32 bits");
-    __shared__ Smem<T, NV, NC> sm;
+    constexpr bool STAGE = (NV == 1) && (KIND == KIND_K);
+    __shared__ Smem<T, NV, NC, STAGE> sm;
 
+    const KTab *kt = ktab_for_kind<KIND>();
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -218,6 +240,10 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                 a.out[i] = res;
                 done |= 1u << r;
             } else if (NV == 1) {
+                if (STAGE) {
+                    sm.sv[e] = v;
+                    sm.sx[e] = x;
+                }
                 b0 = classify_var<T, KIND, VAR>(v, x);
                 if (C::fb > 1 && b0 == BR_FB)
                     b0 = BR_FB + k_cost_bucket<kKBuckets>(double(v), double(x));
@@ -264,6 +290,13 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     }
     __syncthreads();
     if (tid == 0) {
+        int only = -1, present = 0;
+        for (int b = 0; b < NC; ++b)
+            if (sm.start[b] > 0) {
+                only = b;
+                ++present;
+            }
+        sm.uniform = (present == 1) ? only : -1;
         // list order: fallback buckets from costliest down, Debye, Hankel
         int pos = 0;
         for (int b = NC - 1; b >= BR_FB; --b) {
@@ -281,6 +314,25 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     const int n_fb = sm.start[BR_U];              // all fallback buckets
     const int n_fb_u = sm.start[BR_MU];           // ... plus Debye
     const int n_all = sm.n_all;
+
+    // Uniform tile (one class only, e.g. one order whose arguments all fall
+    // in one regime): every wave already runs one branch, so each thread
+    // evaluates its own elements in input order, with coalesced loads and
+    // stores and no list.  The value of an element is the same either way.
+    if (NV == 1 && sm.uniform >= 0) {
+        const int b = (sm.uniform >= BR_FB) ? BR_FB : sm.uniform;
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            if (done & (1u << r))
+                continue;
+            const int e = r * kThreads + tid;
+            const T v = STAGE ? sm.sv[e] : order_of<T, KIND, OP>(a, base + e);
+            const T x = STAGE ? sm.sx[e] : a.x[base + e];
+            const T y = eval_branch<T, KIND, VAR>(b, v, x, kt);
+            a.out[base + e] = combine<T, KIND, OP>(v, x, T(1), a.p, y, y);
+        }
+        return;
+    }
 
     // 3. scatter evaluation ids in list order
 #pragma unroll
@@ -312,21 +364,38 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             const int id = sm.list[j];
             const int e = id / NV;
             const int sub = id - e * NV;
-            const int64_t i = base + e;
             const int b = (j < n_fb) ? BR_FB : (j < n_fb_u ? BR_U : BR_MU);
-            const T v = order_of<T, KIND, OP>(a, i);
-            const T x = a.x[i];
-            const T y = eval_branch<T, KIND, VAR>(b, v + T(sub), x);
-            if (NV == 2) {
-                sm.res[id] = y;
+            if (STAGE) {
+                sm.sv[e] = eval_branch<T, KIND, VAR>(b, sm.sv[e], sm.sx[e], kt);
             } else {
-                const T g = (a.g != nullptr) ? a.g[i] : T(1);
-                a.out[i] = combine<T, KIND, OP>(v, x, g, a.p, y, y);
+                const int64_t i = base + e;
+                const T v = order_of<T, KIND, OP>(a, i);
+                const T x = a.x[i];
+                const T y = eval_branch<T, KIND, VAR>(b, v + T(sub), x, kt);
+                if (NV == 2)
+                    sm.res[id] = y;
+                else
+                    a.out[i] = combine<T, KIND, OP>(v, x, T(1), a.p, y, y);
             }
         }
     }
 
-    // 5. two-order operations: combine per element
+    // 5a. staged operations: coalesced store of the results
+    if (STAGE) {
+        __syncthreads();
+        const T vs = OpTraits<OP>::scalar_order ? a.vs : T(0);   // combine's order (vMF)
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            if (done & (1u << r))
+                continue;
+            const int e = r * kThreads + tid;
+            const T y = sm.sv[e];
+            a.out[base + e] = combine<T, KIND, OP>(vs, sm.sx[e], T(1), a.p, y, y);
+        }
+        return;
+    }
+
+    // 5b. two-order operations: combine per element
     if (NV == 2) {
         __syncthreads();
 #pragma unroll
@@ -374,6 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_sorted_eval(const uint8_t *__restr
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ x,
                                                           double *__restrict__ out, int64_t n) {
+    const KTab *kt = ktab_for_kind<KIND>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
@@ -384,7 +454,7 @@ __global__ __launch_bounds__(kThreads) void k_sorted_eval(const uint8_t *__restr
     if (key[i] == 7)
         special_value<double, KIND>(vv, xx, &y);
     else
-        y = eval_branch<double, KIND, VAR>(int(key[i]), vv, xx);
+        y = eval_branch<double, KIND, VAR>(int(key[i]), vv, xx, kt);
     out[e] = y;
 }
 
@@ -452,6 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, u
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int32_t *nodes,
                                                      int64_t n) {
+    const KTab *kt = ktab_for_kind<KIND_K>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
@@ -460,7 +531,7 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
     int c = 0;
     if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB) {
         if (xx >= T(1e-10))
-            br_k_cosh(double(vv), double(xx), &c);
+            br_k_cosh(double(vv), double(xx), kt, &c);
         else if (vv >= T(0.3))
             c = tables::kQuadN;
     }
@@ -470,13 +541,14 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_branch(int b, const double *v, const double *x,
                                                      double *out, int64_t n) {
+    const KTab *kt = ktab_for_kind<KIND>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
     const double vv = (KIND == KIND_K) ? fabs(v[i]) : v[i];
     double y;
     if (!special_value<double, KIND>(vv, x[i], &y))
-        y = eval_branch<double, KIND>(b, vv, x[i]);
+        y = eval_branch<double, KIND>(b, vv, x[i], kt);
     out[i] = y;
 }
 
@@ -571,8 +643,8 @@ __global__ __launch_bounds__(64) void k_vmf_kappa(const double *__restrict__ sum
     double prev = __builtin_inf();
     bool ok = (R > 0.0) && (R < 1.0) && (n > 0);
     for (; ok && it < 40; ++it) {
-        const double l0 = eval_full<double, KIND_I>(v, k);
-        const double l1 = eval_full<double, KIND_I>(v + 1.0, k);
+        const double l0 = eval_full<double, KIND_I>(v, k, nullptr);
+        const double l1 = eval_full<double, KIND_I>(v + 1.0, k, nullptr);
         const double A = exp(l1 - l0);
         const double kn = k - (A - R) / (1.0 - A * A - (p - 1.0) * A / k);
         const double d = fabs(kn - k);

@@ -18,6 +18,7 @@ were taken on (the benchmark reports them only while the sources match).
 """
 import hashlib
 import json
+import re
 import os
 import sys
 
@@ -46,7 +47,7 @@ def _read(csv_path: str, counter: str):
             name, val = row["Kernel_Name"], float(row["Counter_Value"])
             if "copyBuffer" in name:             # the runtime's device-to-device copy
                 copy = val
-            elif "k_grouped<double, 1, 0>" in name:
+            elif re.search(r"k_grouped<double, 1, 0(, 0)?>", name):
                 launch = val
     if copy is None or launch is None:
         raise SystemExit(f"{csv_path}: copy or log K dispatch not found for {counter}")

@@ -88,7 +88,7 @@ def test_binding_refuses_cpu_tensors():
 def test_segment_and_fit_argument_checks(lib):
     lib.lbessel_segment_tiles.restype = ctypes.c_int64
     lib.lbessel_segment_tiles.argtypes = [ctypes.c_int64]
-    assert [lib.lbessel_segment_tiles(n) for n in (0, 1, 2048, 2049)] == [0, 1, 1, 2]
+    assert [lib.lbessel_segment_tiles(n) for n in (0, 1, 1024, 1025)] == [0, 1, 1, 2]
     assert lib.lbessel_segment_tiles(-1) == -1
     assert lib.lbessel_eval_segments(0, 64, None, 0, 0, None) == 0         # empty batch
     assert lib.lbessel_eval_segments(2, 64, None, 0, 0, None) == -1        # bad kind
