@@ -490,23 +490,39 @@ __device__ __forceinline__ void ktab_load(KTab *t) {
 __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
                                             int *nodes = nullptr) {
     constexpr double kGrid = 1.0 / 64.0;
-    constexpr double kDrop = 45.0;          // e^-45 ~ 3e-20 of the peak term
+    constexpr double kDrop = 40.0;          // e^-40 ~ 4e-18 of the peak term
     constexpr int kMaxNodes = 1024;         // every walk ends (window <= ~40 / h)
-    // peak: x sinh t = v tanh(v t); Newton from asinh(v/x), which lies right of
-    // the root of this convex increasing function, so iterates decrease to it
+    // peak: root t* > 0 of psi(t) = x sinh t - v tanh(v t) (convex on t >= 0,
+    // psi(0) = 0, psi'(0) = x - v^2 < 0).  tanh(vt) <= 1 and tanh(vt) <= vt
+    // give t* <= asinh(v/x) and t* <= t_s, sinh(t_s)/t_s = v^2/x; two steps of
+    // t <- asinh(R t) from asinh(R), R = v^2/x, approach t_s from below.
+    // Newton starts at the smaller of asinh(v/x) and that estimate: from the
+    // right of t* it decreases monotonically, from the left (where psi' > 0)
+    // its first step lands right of t*; where psi' <= 0 it restarts from the
+    // bound asinh(v/x).  t0 is rounded to the 1/64 grid, so |dt| < 4e-3 ends it.
     double t = 0.0;
     if (v * v > x) {
         const double q = v / x;
-        t = fm::log64(q + sqrt(fma(q, q, 1.0)));
+        const double R = v * q;
+        auto asinh_pos = [](double a) { return fm::log64(a + sqrt(fma(a, a, 1.0))); };
+        const double tu = asinh_pos(q);
+        double ts = asinh_pos(R);
+        ts = asinh_pos(R * ts);
+        ts = asinh_pos(R * ts);
+        t = fmin(tu, ts);
         for (int it = 0; it < 16; ++it) {
             const double e = fm::exp64(t), r = fm::rcp_nr(e);
             const double z = fm::exp64(-2.0 * v * t);
             const double iz = fm::rcp_nr(1.0 + z);
             const double psi = fma(0.5 * x, e - r, -v * (1.0 - z) * iz);
             const double dpsi = fma(0.5 * x, e + r, -4.0 * v * v * z * iz * iz);
+            if (!(dpsi > 0.0)) {   // left of psi's minimum
+                t = tu;
+                continue;
+            }
             const double dt = psi * fm::rcp_nr(dpsi);
             t = fmax(t - dt, 0.0);
-            if (fabs(dt) < 1e-4)
+            if (fabs(dt) < 4e-3)
                 break;
         }
     }

@@ -1,0 +1,101 @@
+"""The K fallback's cosh-integral rule at its own internal boundaries, against
+the binary128 oracle: the switch between a window that starts at t = 0 and
+an interior window (including walks that step past t = 0 and use the mirror
+node of the even integrand), the x = 1e-10 switch to the small-argument
+forms, orders near zero, and the node counts the op model relies on."""
+import numpy as np
+import pytest
+import torch
+
+from parity import TOL64, TOL32, cond_err
+
+pytestmark = pytest.mark.gpu
+
+# inputs whose interior window's left walk steps past t = 0 (found by a
+# float64 model of the rule; about 0.1% of random small-x fallback inputs)
+MIRROR = [
+    (float.fromhex('0x1.193ca9819d1d3p+2'), float.fromhex('0x1.854d6cb5f349ap-14')),
+    (float.fromhex('0x1.2022ac10b1ef6p+1'), float.fromhex('0x1.496fdc71f506ap-29')),
+    (float.fromhex('0x1.fcbd1317db53ap+1'), float.fromhex('0x1.e1f2a0fda44b3p-16')),
+    (float.fromhex('0x1.a704f2936e64cp+1'), float.fromhex('0x1.167457e0dd052p-19')),
+    (float.fromhex('0x1.9140245b684f5p+2'), float.fromhex('0x1.7de2183eda95fp-9')),
+    (float.fromhex('0x1.39d3174c62361p+2'), float.fromhex('0x1.3741858e2a95ep-12')),
+    (float.fromhex('0x1.06b0a66743e37p+1'), float.fromhex('0x1.5f301a2281cdep-32')),
+    (float.fromhex('0x1.cf53040a0419dp+1'), float.fromhex('0x1.1677cf20b654cp-17')),
+    (float.fromhex('0x1.77e6c54ca33adp+2'), float.fromhex('0x1.c42e6f190492ap-10')),
+    (float.fromhex('0x1.9527509075b6fp+1'), float.fromhex('0x1.322f053a0a2d8p-20')),
+    (float.fromhex('0x1.4843403bcc23dp+1'), float.fromhex('0x1.26a1a6bc5f6e0p-25')),
+    (float.fromhex('0x1.31a794709bc9bp+3'), float.fromhex('0x1.b591fd1cad876p-5')),
+    (float.fromhex('0x1.20609de1c12b4p+3'), float.fromhex('0x1.44a87053d84b9p-5')),
+    (float.fromhex('0x1.9e45e5ea4bf36p+1'), float.fromhex('0x1.d457ad9b245ccp-20')),
+    (float.fromhex('0x1.5f88bf1e253d4p+1'), float.fromhex('0x1.df86b649921e8p-24')),
+    (float.fromhex('0x1.a6871539a45f0p+2'), float.fromhex('0x1.3585fa51edfc5p-8')),
+    (float.fromhex('0x1.3035e677acb53p+3'), float.fromhex('0x1.ae5663a101324p-5')),
+    (float.fromhex('0x1.13b7c59b7cc59p+1'), float.fromhex('0x1.eb27c1251f8e4p-31')),
+    (float.fromhex('0x1.0b203fc11cc2ap+1'), float.fromhex('0x1.ca02ca8d9fc2fp-32')),
+    (float.fromhex('0x1.0a4abf96cb4b3p+1'), float.fromhex('0x1.d28dc80ede9bdp-32')),
+    (float.fromhex('0x1.4b31b3e72a154p+3'), float.fromhex('0x1.7b5cd09aaf3e8p-4')),
+    (float.fromhex('0x1.56118796abbfep+2'), float.fromhex('0x1.8ec9cf631da7dp-11')),
+    (float.fromhex('0x1.8f3ca5b2c854dp+2'), float.fromhex('0x1.84473db0d1b23p-9')),
+    (float.fromhex('0x1.f73591200af72p+0'), float.fromhex('0x1.ce5f265eed5bdp-34')),
+]
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the -m gpu tests need an MI355X")
+    import paper_2409_08729_amd as m
+    m.lib()
+    return m
+
+
+def _check(lb, oracle, v, x, dtype=torch.float64):
+    v = np.asarray(v, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    if dtype == torch.float32:
+        v = v.astype(np.float32).astype(np.float64)
+        x = x.astype(np.float32).astype(np.float64)
+    dv = torch.from_numpy(v).to("cuda:0", dtype)
+    dx = torch.from_numpy(x).to("cuda:0", dtype)
+    y = lb.log_kv(dv, dx).double().cpu().numpy()
+    hi, lo = oracle.log_kv(v, x)
+    assert np.array_equal(np.isfinite(y), np.isfinite(hi))
+    e = cond_err(y, hi, lo, v, x)
+    return e
+
+
+def test_walks_past_zero(lb, oracle):
+    v, x = np.array(MIRROR).T
+    e = _check(lb, oracle, v, x)
+    assert e.max() <= TOL64, e.max()
+    # the same points perturbed: both sides of the window switch
+    for s in (1 - 1e-3, 1 + 1e-3, 0.97, 1.03):
+        assert _check(lb, oracle, v, x * s).max() <= TOL64
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_small_argument_switch(lb, oracle, dtype):
+    vs = np.array([0.0, 1e-8, 0.05, 0.1, 0.29, 0.2999999, 0.3, 0.3000001, 0.31, 0.5, 1.0, 3.7,
+                   9.0, 14.4])
+    xs = 1e-10 * np.array([1 - 1e-6, 1 - 1e-12, 1.0, 1 + 1e-12, 1 + 1e-6, 0.5, 2.0])
+    v, x = np.meshgrid(vs, xs)
+    e = _check(lb, oracle, v.ravel(), x.ravel(), dtype)
+    assert e.max() <= (TOL64 if dtype == torch.float64 else TOL32), e.max()
+
+
+def test_orders_near_zero(lb, oracle):
+    g = np.random.default_rng(12)
+    v = np.concatenate([10 ** g.uniform(-300, -3, 800), np.zeros(100)])
+    x = 10 ** g.uniform(-10, np.log10(17.0), 900)
+    e = _check(lb, oracle, v, x)
+    assert e.max() <= TOL64, e.max()
+
+
+def test_node_counts_on_the_stress_grid(lb):
+    from paper_2409_08729_amd import workloads as wl
+    v, x = wl.m3(1 << 20)
+    n = lb.k_nodes(torch.from_numpy(v).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    fb = n > 0
+    assert 0.3 < fb.mean() < 0.5
+    assert 20 < n[fb].mean() < 60 and n.max() < 400, (n[fb].mean(), n.max())
