@@ -85,14 +85,26 @@ def one_step(lb, torch, sets, outs, timers=None):
                 timers.append((name, kind, e0, e1))
 
 
+# Debye term-count tiers of the library (u_tier in lbessel_device.hpp):
+# U_13 up to v = 26, U_9 up to 60, U_6 up to 190, U_4 above
+U_TIER_CUTS = (26.0, 60.0, 190.0)
+
+
 def op_counts(lb, torch, sets):
-    """Branch mix of every set (lbessel_classify) and the total integrand node
-    count of the K fallback elements (lbessel_k_nodes) for the op model."""
+    """Branch mix of every set (lbessel_classify; Debye elements split by
+    term-count tier) and the total integrand node count of the K fallback
+    elements (lbessel_k_nodes) for the op model."""
     mix, nodes = {}, {}
+    cuts = torch.tensor(U_TIER_CUTS, dtype=torch.float64, device=sets[0][1].device)
     for j, (name, v, x) in enumerate(sets):
         for kind in ("I", "K"):
-            b = lb.classify(kind, v, x)
-            mix[(j, kind)] = torch.bincount(b.to(torch.int64), minlength=4).cpu().tolist()
+            b = lb.classify(kind, v, x).to(torch.int64)
+            c = torch.bincount(b, minlength=4).cpu().tolist()
+            vu = v[b == 1].abs()
+            tiers = torch.bucketize(vu, cuts)     # v > cut: 0 = U_13 ... 3 = U_4
+            c_u = torch.bincount(tiers, minlength=4).cpu().tolist()
+            mix[(j, kind)] = {"mu20": c[0], "u13": c_u[0], "u9": c_u[1], "u6": c_u[2],
+                              "u4": c_u[3], "fallback": c[2], "special": c[3]}
         nodes[j] = int(lb.k_nodes(v, x).to(torch.int64).sum().item())
     return mix, nodes
 
@@ -138,6 +150,7 @@ def sample_errors(torch, outs, sample):
     res = {}
     for kind, col in (("I", 3), ("K", 4)):
         worst_c, worst_r, npts = 0.0, 0.0, 0
+        all_c, all_r = [], []
         for blk in sample:
             ids, v, x = blk[0], blk[1], blk[2]
             hi, lo = blk[col]
@@ -151,7 +164,11 @@ def sample_errors(torch, outs, sample):
                 rel = np.where(hi[fin] != 0, d / np.abs(hi[fin]), 0.0)
             worst_r = max(worst_r, float(rel.max(initial=0.0)))
             npts += int(fin.sum())
-        res[kind] = {"max_cond_err": worst_c, "max_rel_err": worst_r, "points": npts}
+            all_c.append(d / den)
+            all_r.append(rel)
+        res[kind] = {"max_cond_err": worst_c, "max_rel_err": worst_r, "points": npts,
+                     "hist_cond_err": histogram(np.concatenate(all_c)),
+                     "hist_rel_err": histogram(np.concatenate(all_r))}
     return res
 
 
@@ -204,6 +221,46 @@ ABLATIONS = (  # (variant, layout): the paper's own choices put back one at a ti
     ("paper", "grouped"), ("paper", "sorted"), ("paper", "naive"),
     ("seven", "naive"), ("seven", "sorted"),
 )
+
+
+DECADES = [10.0 ** k for k in range(-18, -1)]
+
+
+def histogram(err):
+    """Counts per decade bin of the error: [0, 1e-18), [1e-18, 1e-17), ..., >= 1e-2."""
+    edges = np.array(DECADES)
+    idx = np.searchsorted(edges, err, side="right")
+    counts = np.bincount(idx, minlength=len(edges) + 1)
+    labels = ["<1e-18"] + [f"[1e{k},1e{k + 1})" for k in range(-18, -2)] + [">=1e-2"]
+    return dict(zip(labels, counts.tolist()))
+
+
+def f32_errors(torch, sets32, outs32, per_set=1 << 11):
+    """Per-result error of the timed binary32 outputs against the oracle at the
+    binary32 inputs (widened exactly), on a seeded sample of every set: the
+    parity measure |y - ref| / max(|ref|, 1 + |(v, x)|) and the plain
+    relative error, with their decade histograms."""
+    from oracle import oracle
+    rng = np.random.default_rng(6)
+    res = {}
+    for kind in ("I", "K"):
+        cond, rel = [], []
+        for j, (name, v, x) in enumerate(sets32):
+            idx = torch.from_numpy(rng.integers(0, v.numel(), per_set)).to(v.device)
+            hv = v[idx].double().cpu().numpy()
+            hx = x[idx].double().cpu().numpy()
+            y = outs32[(j, kind)][idx].double().cpu().numpy()
+            hi, lo = (oracle.log_iv if kind == "I" else oracle.log_kv)(hv, hx)
+            fin = np.isfinite(hi)
+            d = np.abs((y[fin] - hi[fin]) - lo[fin])
+            cond.append(d / np.maximum(np.abs(hi[fin]), 1.0 + np.hypot(hv[fin], hx[fin])))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                rel.append(np.where(hi[fin] != 0, d / np.abs(hi[fin]), 0.0))
+        cond, rel = np.concatenate(cond), np.concatenate(rel)
+        res[kind] = {"points": int(cond.size), "max_cond_err": float(cond.max()),
+                     "max_rel_err": float(rel.max()), "hist_cond_err": histogram(cond),
+                     "hist_rel_err": histogram(rel)}
+    return {"sample": f"{per_set} seeded points per set at the binary32 inputs", **res}
 
 
 def ablation_bench(lb, torch, sets, sample=1 << 13):
@@ -419,8 +476,8 @@ def main():
 
     def k_ops(j):
         c = mix[(j, "K")]
-        return (c[0] * ck["mu20"] + c[1] * ck["u13"] + c[2] * ck["fallback_setup"]
-                + knodes[j] * ck["fallback_per_node"])
+        return (c["mu20"] * ck["mu20"] + sum(c[u] * ck[u] for u in ("u13", "u9", "u6", "u4"))
+                + c["fallback"] * ck["fallback_setup"] + knodes[j] * ck["fallback_per_node"])
 
     js = len(sets) - 1
     ops = k_ops(js)
@@ -433,10 +490,10 @@ def main():
             "kernel": "k_grouped<double, K, log> (lbessel_log_kv_f64)",
             "launch": f"{sets[js][0]}: {sets[js][1].numel()} pairs",
             "ops_per_launch": ops, "launch_ms": dur * 1e3,
-            "branch_counts": dict(zip(("mu20", "u13", "fallback", "special"), mix[(js, "K")])),
+            "branch_counts": mix[(js, "K")],
             "fallback_nodes": knodes[js],
-            "op_model": "mu20 x n_mu + u13 x n_u + fallback_setup x n_fb + "
-                        "fallback_per_node x nodes (paper_2409_08729_amd/opmodel.json)",
+            "op_model": "mu20 x n_mu + sum over Debye tiers uK x n_uK + fallback_setup x n_fb"
+                        " + fallback_per_node x nodes (paper_2409_08729_amd/opmodel.json)",
             "algorithmic_bytes_per_launch": 24 * sets[js][1].numel(),
             "all_K_launches": {"frac": all_ops / all_dur / 1e12 / VALU_PEAK_TOPS,
                                "ms": all_dur * 1e3}}
@@ -476,6 +533,8 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         f32 = {"value": evals / dt / 1e9, "unit": "G evals/s", "ms_per_step": dt * 1e3}
+        if not args.no_cpu_baseline:
+            f32["errors"] = f32_errors(torch, sets32, o32)
         del sets32, o32
 
     ablations = None

@@ -28,8 +28,9 @@
  *      arrive while batches are on the GPU are admitted as memory frees up
  *      and go out with the next batch; up to `streams` batches overlap
  *      (copies of one with kernels of another).
- *   4. completion: when a batch's event fires its requests are done and
- *      their arena regions are released.
+ *   4. completion: each request completes, and releases its arena region,
+ *      as soon as the copy of its own results has finished (one event per
+ *      request on the batch's stream).
  * Plain mode runs the same queue and admission but launches each request
  * on its own with the single-array entry points (one launch per request,
  * one request per stream): the baseline the batching is measured against.
@@ -67,7 +68,7 @@ typedef struct lbessel_server_config {
     int64_t arena_bytes;        /* device arena for request data (> 0)           */
     int streams;                /* batches (plain: requests) in flight, 1..16   */
     int mode;                   /* LBESSEL_SERVE_BATCHED or LBESSEL_SERVE_PLAIN  */
-    int max_batch_requests;     /* requests per batch, 1..65536                  */
+    int max_batch_requests;     /* requests per batch, 1..1024                   */
     int64_t max_batch_elems;    /* evaluation pairs per batch (>= 1); a single
                                    larger request still forms a batch alone    */
     int poll_us;                /* scheduler sleep while batches run; 0 = spin  */
@@ -105,8 +106,8 @@ typedef struct lbessel_server_stats {
     int64_t max_batch_requests_seen;
 } lbessel_server_stats_t;
 
-/* Default configuration: 2 GiB arena, 4 streams, batched, 4096 requests and
- * 2^26 pairs per batch, spinning scheduler. */
+/* Default configuration: 2 GiB arena, 4 streams, batched, 64 requests and
+ * 2^22 pairs per batch, spinning scheduler. */
 void lbessel_server_default_config(lbessel_server_config_t *cfg);
 
 /*

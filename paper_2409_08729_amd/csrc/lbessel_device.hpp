@@ -54,6 +54,9 @@ __device__ __forceinline__ float lexp(float a) { return expf(a); }
 __device__ __forceinline__ float llog(float a) { return logf(a); }
 // exp of an argument known to satisfy |a| < 1e9
 __device__ __forceinline__ double lexp_b(double a) { return fm::exp64_bounded(a); }
+// reciprocal: Newton-refined hardware estimate in binary64 (<= 1 ulp)
+__device__ __forceinline__ double lrcp(double a) { return fm::rcp_nr(a); }
+__device__ __forceinline__ float lrcp(float a) { return 1.0f / a; }
 __device__ __forceinline__ float lexp_b(float a) { return expf(a); }
 
 // ---------------------------------------------------------------------------
@@ -249,7 +252,10 @@ template <> __device__ __forceinline__ const float (*debye_table<float>())[14] {
 // NT Debye terms (U_NT); the library uses NT = 13, the seven-branch variant
 // of Algorithm 1 also U_4, U_6 and U_9.
 template <typename T, int KIND, int NT = tables::kUTerms>
-__device__ __forceinline__ T br_u(T v, T x) {
+// nt (<= NT, runtime): terms actually summed.  Terms above nt are skipped
+// per lane, so lanes of one wave with different nt cost the largest nt once,
+// and a term count gives the same bits whichever way it is reached.
+__device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
     const T z = x / v;
     const T r = (z < Cst<T>::big_z) ? sqrt(fma(z, z, T(1))) : z;
     const T t = T(1) / r;
@@ -259,6 +265,8 @@ __device__ __forceinline__ T br_u(T v, T x) {
     T acc = T(0);
 #pragma unroll
     for (int k = NT; k >= 1; --k) {
+        if (k > nt)
+            continue;
         const LB_CONST_AS T *row = P + 14 * (k - 1);
         T pk = fm::fma_c(row[k], p, row[k - 1]);
 #pragma unroll
@@ -297,7 +305,7 @@ __device__ __forceinline__ T br_series_i(T v, T x) {
     for (int k = 1; k < 200; ++k) {
         const T fk = T(k);
         const T den = fk * (fk + v);
-        term = term * q / den;
+        term = term * q * lrcp(den);
         sum = sum + term;
         if (den > T(2) * q && term < Cst<T>::series_eps * sum)
             break;
@@ -581,6 +589,25 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     return M + fm::log64(0.5 * h * S);
 }
 
+// Debye term-count tier of an order on the Debye branch: 0 = U_13, 1 = U_9,
+// 2 = U_6, 3 = U_4.  U_K's truncation error, relative to max(|y|, 1 + |(v, x)|),
+// is below 1e-15 for every x once v >= 14.2 (K = 13), 24 (9), 56 (6) and
+// 176 (4) (error maps against the oracle, I and K); the cuts keep ~8% margin.
+constexpr int kUTiers = 4;
+template <typename T>
+__device__ __forceinline__ int u_tier(T v) {
+    return (v > T(190)) ? 3 : (v > T(60)) ? 2 : (v > T(26)) ? 1 : 0;
+}
+
+// Cost bucket 0..B-1 of an I series element: its term count grows with x
+// (about 3 terms below x = 0.01, 8 at x = 1, 18 at x = 6, 33 at x = 20).
+// Only used to order work inside a tile; any value is correct.
+template <int B, typename T>
+__device__ __forceinline__ int i_cost_bucket(T x) {
+    static_assert(B == 4, "thresholds are set for four buckets");
+    return (x < T(0.1)) ? 0 : (x < T(1)) ? 1 : (x < T(5)) ? 2 : 3;
+}
+
 // Cost bucket 0..B-1 of a K fallback element: a rough count of the nodes
 // br_k_cosh will visit (window width / step), cut at fixed thresholds.  Only
 // used to order work inside a tile; any value is correct.
@@ -701,8 +728,13 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const KTab *kt) {
     }
     if (b == BR_MU)
         return br_mu<T, KIND>(v, x);
-    if (b == BR_U)
+    if (b == BR_U) {
+        if (VAR == VAR_DEFAULT) {
+            const int tr = u_tier(v);
+            return br_u<T, KIND>(v, x, (tr == 3) ? 4 : (tr == 2) ? 6 : (tr == 1) ? 9 : 13);
+        }
         return br_u<T, KIND>(v, x);
+    }
     if (KIND == KIND_I)
         return br_series_i<T>(v, x);
     constexpr bool u_integral = (VAR == VAR_U_INTEGRAL || VAR == VAR_SIMPSON || VAR == VAR_PAPER);

@@ -159,18 +159,27 @@ template <int NV> struct TileCfg {
 };
 
 // Classes an evaluation is sorted into inside a tile: 0 = Hankel, 1 = Debye,
-// 2 + b = fallback bucket b.  The K fallback's cost varies ~10x with (v, x)
-// (its node count), so for the forward K path it is split into kKBuckets
-// buckets by an estimate of that count; lanes of one 64-entry chunk then
-// run loops of similar length.  List order: costliest bucket first, then
-// the cheaper ones, Debye, Hankel.
+// 2 + b = fallback bucket b.  The fallbacks' costs vary ~10x with (v, x):
+// the K integral's node count and the I series' term count.  For the
+// one-order operations the fallback is therefore split into buckets by an
+// estimate of that count (kKBuckets for K, kIBuckets for I), so the lanes of
+// one 64-entry chunk run loops of similar length.  List order: costliest
+// bucket first, then the cheaper ones, Debye, Hankel.
+// The Debye class is split the same way into its term-count tiers (U_13,
+// U_9, U_6, U_4; u_tier), which differ ~2x in cost.
+// Class ids: 0 = Hankel, 1..ub = Debye tier, 1+ub.. = fallback bucket.
 constexpr int kKBuckets = 6;
+constexpr int kIBuckets = 4;
 template <int KIND, int OP, int VAR> struct Classes {
-    static constexpr int fb = (KIND == KIND_K && OpTraits<OP>::nv == 1 &&
-                               (VAR == VAR_DEFAULT || VAR == VAR_PAPER_REGIMES))
-                                  ? kKBuckets
-                                  : 1;
-    static constexpr int n = 2 + fb;
+    static constexpr bool one = (OpTraits<OP>::nv == 1);
+    static constexpr int fb =
+        !one ? 1
+        : (KIND == KIND_K) ? ((VAR == VAR_DEFAULT || VAR == VAR_PAPER_REGIMES) ? kKBuckets : 1)
+                           : kIBuckets;
+    static constexpr int ub = (one && VAR == VAR_DEFAULT) ? kUTiers : 1;
+    static constexpr int u0 = 1;          // first Debye class
+    static constexpr int f0 = 1 + ub;     // first fallback class
+    static constexpr int n = 1 + ub + fb;
     static constexpr int bits = (n > 3) ? 4 : 2;
     static constexpr int none = (1 << bits) - 1;
 };
@@ -187,7 +196,7 @@ template <typename T, int NV, int NC, bool STAGE> struct Smem {
     uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, class-sorted
     int cnt[NC][TileCfg<NV>::slots][kWaves];             // counts, then offsets
     int start[NC];                                       // first list position per class
-    int n_all;
+    int n_fb, n_fb_u, n_all;                             // list segment ends
     int uniform;                                         // the only class present, or -1
     int chunk;                                           // next chunk to evaluate
     T res[(NV == 2) ? TileCfg<NV>::tile * 2 : 1];        // log-values of both orders
@@ -211,6 +220,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     constexpr int BITS = C::bits;
     constexpr uint32_t MASK = (1u << BITS) - 1;
     static_assert(SLOTS * BITS <= 32, "class codes of one thread fit 32 bits");
+    static_assert(NC * SLOTS <= 64, "one lane clears each (class, slot) count");
     constexpr bool STAGE = (NV == 1) && (KIND == KIND_K);
     __shared__ Smem<T, NV, NC, STAGE> sm;
 
@@ -244,9 +254,15 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                     sm.sv[e] = v;
                     sm.sx[e] = x;
                 }
-                b0 = classify_var<T, KIND, VAR>(v, x);
-                if (C::fb > 1 && b0 == BR_FB)
-                    b0 = BR_FB + k_cost_bucket<kKBuckets>(double(v), double(x));
+                const int br = classify_var<T, KIND, VAR>(v, x);
+                if (br == BR_MU)
+                    b0 = 0;
+                else if (br == BR_U)
+                    b0 = C::u0 + ((C::ub > 1) ? u_tier(v) : 0);
+                else
+                    b0 = C::f0 + ((C::fb == 1) ? 0
+                                  : (KIND == KIND_K) ? k_cost_bucket<kKBuckets>(double(v), double(x))
+                                                     : i_cost_bucket<kIBuckets>(x));
             } else {
                 T ys;
                 if (special_value<T, KIND>(v, x, &ys))
@@ -265,12 +281,25 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             code |= uint32_t(b1) << (BITS * (r * NV + 1));
     }
 
-    // 2. per-wave counts per (class, slot), then offsets within each class
+    // 2. per-wave counts per (class, slot), then offsets within each class.
+    //    Only the classes present in the wave take ballots (OR of the lanes'
+    //    class masks); the others count 0.
+    uint32_t present = 0;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s)
+        present |= 1u << ((code >> (BITS * s)) & MASK);
+    present &= ~(1u << C::none);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        present |= uint32_t(__shfl_xor(int(present), off));
+    present = __builtin_amdgcn_readfirstlane(present);
+    if (lane < NC * SLOTS)
+        sm.cnt[lane / SLOTS][lane % SLOTS][wave] = 0;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int b = (code >> (BITS * s)) & MASK;
-#pragma unroll
-        for (int br = 0; br < NC; ++br) {
+        for (uint32_t pm = present; pm != 0; pm &= pm - 1) {
+            const int br = __builtin_ctz(pm);
             const uint64_t m = __ballot(b == br);
             if (lane == 0)
                 sm.cnt[br][s][wave] = __popcll(m);
@@ -290,29 +319,36 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     }
     __syncthreads();
     if (tid == 0) {
-        int only = -1, present = 0;
+        int only = -1, nclass = 0;
         for (int b = 0; b < NC; ++b)
             if (sm.start[b] > 0) {
                 only = b;
-                ++present;
+                ++nclass;
             }
-        sm.uniform = (present == 1) ? only : -1;
-        // list order: fallback buckets from costliest down, Debye, Hankel
+        sm.uniform = (nclass == 1) ? only : -1;
+        // list order: fallback buckets from costliest down, Debye tiers from
+        // costliest (U_13) down, Hankel
         int pos = 0;
-        for (int b = NC - 1; b >= BR_FB; --b) {
+        for (int b = NC - 1; b >= C::f0; --b) {
             const int t = sm.start[b];
             sm.start[b] = pos;
             pos += t;
         }
-        const int tu = sm.start[BR_U], tm = sm.start[BR_MU];
-        sm.start[BR_U] = pos;
-        sm.start[BR_MU] = pos + tu;
-        sm.n_all = pos + tu + tm;
+        sm.n_fb = pos;
+        for (int b = C::u0; b < C::f0; ++b) {
+            const int t = sm.start[b];
+            sm.start[b] = pos;
+            pos += t;
+        }
+        sm.n_fb_u = pos;
+        const int tm = sm.start[0];
+        sm.start[0] = pos;
+        sm.n_all = pos + tm;
         sm.chunk = 0;
     }
     __syncthreads();
-    const int n_fb = sm.start[BR_U];              // all fallback buckets
-    const int n_fb_u = sm.start[BR_MU];           // ... plus Debye
+    const int n_fb = sm.n_fb;                     // all fallback buckets
+    const int n_fb_u = sm.n_fb_u;                 // ... plus Debye
     const int n_all = sm.n_all;
 
     // Uniform tile (one class only, e.g. one order whose arguments all fall
@@ -320,7 +356,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     // evaluates its own elements in input order, with coalesced loads and
     // stores and no list.  The value of an element is the same either way.
     if (NV == 1 && sm.uniform >= 0) {
-        const int b = (sm.uniform >= BR_FB) ? BR_FB : sm.uniform;
+        const int b = (sm.uniform >= C::f0) ? BR_FB : (sm.uniform >= C::u0 ? BR_U : BR_MU);
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             if (done & (1u << r))
@@ -338,8 +374,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int b = (code >> (BITS * s)) & MASK;
-#pragma unroll
-        for (int br = 0; br < NC; ++br) {
+        for (uint32_t pm = present; pm != 0; pm &= pm - 1) {
+            const int br = __builtin_ctz(pm);
             const uint64_t m = __ballot(b == br);
             if (b == br) {
                 const int pos = sm.start[br] + sm.cnt[br][s][wave] + rank_below(m);

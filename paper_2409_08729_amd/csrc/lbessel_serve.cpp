@@ -94,12 +94,18 @@ struct Request {
     int64_t span() const { return align_up(n * elem()); }   // one array in the arena
 };
 
+// One stream with the batch it runs.  Every request of the batch gets its own
+// completion event, recorded right after its result copy, so it completes as
+// soon as its own outputs are back rather than with the whole batch; events
+// on one stream complete in the order they were recorded.
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    std::vector<hipEvent_t> ev;          // one per request of a batch
     lbessel_segment_t *hseg = nullptr;   // pinned staging, kGroups * cap entries
     lbessel_segment_t *dseg = nullptr;   // device copy
-    std::vector<Request *> reqs;
+    std::vector<Request *> reqs;         // the batch
+    std::vector<Request *> order;        // requests in event-record order
+    size_t next_done = 0;                // first entry of order not yet complete
     bool busy = false;
 };
 
@@ -165,6 +171,8 @@ int lbessel_server::enqueue(Slot &sl, int64_t *launches) {
         char *work = arena_dev + r->off + kVmfResult;
         keep(lbessel_vmf_fit_f32(r->X, r->n, r->p, res, work, r->info.bytes - kVmfResult, st));
         hip(hipMemcpyAsync(r->hres, res, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        hip(hipEventRecord(sl.ev[sl.order.size()], st));
+        sl.order.push_back(r);
     }
     // Evaluation requests, one group per (kind, precision).
     for (int g = 0; g < kGroups; ++g) {
@@ -211,18 +219,21 @@ int lbessel_server::enqueue(Slot &sl, int64_t *launches) {
             ++*launches;
         }
         for (Request *r : sl.reqs) {
-            if (r->type != REQ_EVAL || r->group() != g || r->n == 0)
+            if (r->type != REQ_EVAL || r->group() != g)
                 continue;
-            const char *dout = arena_dev + r->off + 2 * r->span();
-            hip(hipMemcpyAsync(r->hout, dout, r->n * r->elem(), hipMemcpyDeviceToHost, st));
+            if (r->n > 0) {
+                const char *dout = arena_dev + r->off + 2 * r->span();
+                hip(hipMemcpyAsync(r->hout, dout, r->n * r->elem(), hipMemcpyDeviceToHost, st));
+            }
+            hip(hipEventRecord(sl.ev[sl.order.size()], st));
+            sl.order.push_back(r);
         }
     }
-    hip(hipEventRecord(sl.done, st));
     return rc;
 }
 
 void lbessel_server::run() {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);   // the device was valid at create
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         bool progress = false;
@@ -231,16 +242,14 @@ void lbessel_server::run() {
         for (Slot &sl : slots) {
             if (!sl.busy)
                 continue;
-            const hipError_t e = hipEventQuery(sl.done);
-            if (e == hipErrorNotReady) {
-                ++busy;
-                continue;
-            }
-            const double t = now();
-            for (Request *r : sl.reqs) {
+            while (sl.next_done < sl.order.size()) {
+                const hipError_t e = hipEventQuery(sl.ev[sl.next_done]);
+                if (e == hipErrorNotReady)
+                    break;
+                Request *r = sl.order[sl.next_done++];
                 if (e != hipSuccess && r->info.status == LBESSEL_OK)
                     r->info.status = LBESSEL_EHIP;
-                r->info.t_done = t;
+                r->info.t_done = now();
                 r->info.state = LBESSEL_REQ_DONE;
                 arena->release(r->off, r->info.bytes);
                 ++stats.completed;
@@ -248,10 +257,16 @@ void lbessel_server::run() {
                     stats.eval_pairs += r->n;
                 else
                     ++stats.vmf_fits;
+                progress = true;
             }
-            sl.reqs.clear();
-            sl.busy = false;
-            progress = true;
+            if (sl.next_done == sl.order.size()) {
+                sl.reqs.clear();
+                sl.order.clear();
+                sl.next_done = 0;
+                sl.busy = false;
+            } else {
+                ++busy;
+            }
         }
         if (progress)
             cv_done.notify_all();
@@ -309,6 +324,14 @@ void lbessel_server::run() {
             if (rc != LBESSEL_OK)
                 for (Request *r : sl.reqs)
                     r->info.status = rc;
+            if (sl.order.size() != sl.reqs.size()) {
+                // an event could not be recorded: finish the batch at once
+                // after the stream drains, so no request waits forever
+                (void)hipStreamSynchronize(sl.stream);
+                sl.order = sl.reqs;
+                for (size_t k = 0; k < sl.order.size(); ++k)
+                    (void)hipEventRecord(sl.ev[k], sl.stream);
+            }
             continue;   // look again at once: more may be launchable
         }
         if (stopping && queue.empty() && admitted.empty() && busy == 0)
@@ -364,15 +387,15 @@ void lbessel_server_default_config(lbessel_server_config_t *cfg) {
     cfg->arena_bytes = int64_t(2) << 30;
     cfg->streams = 4;
     cfg->mode = LBESSEL_SERVE_BATCHED;
-    cfg->max_batch_requests = 4096;
-    cfg->max_batch_elems = int64_t(1) << 26;
+    cfg->max_batch_requests = 64;
+    cfg->max_batch_elems = int64_t(1) << 22;
     cfg->poll_us = 0;
 }
 
 int lbessel_server_create(const lbessel_server_config_t *cfg, lbessel_server_t **out) {
     if (cfg == nullptr || out == nullptr || cfg->arena_bytes <= 0 || cfg->streams < 1 ||
         cfg->streams > 16 || (cfg->mode != LBESSEL_SERVE_BATCHED && cfg->mode != LBESSEL_SERVE_PLAIN) ||
-        cfg->max_batch_requests < 1 || cfg->max_batch_requests > 65536 ||
+        cfg->max_batch_requests < 1 || cfg->max_batch_requests > 1024 ||
         cfg->max_batch_elems < 1 || cfg->poll_us < 0)
         return LBESSEL_EINVAL;
     *out = nullptr;
@@ -393,19 +416,22 @@ int lbessel_server_create(const lbessel_server_config_t *cfg, lbessel_server_t *
     bool ok = true;
     for (Slot &sl : s->slots) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        sl.ev.assign(size_t(cfg->max_batch_requests), nullptr);
+        for (hipEvent_t &e : sl.ev)
+            ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipHostMalloc(reinterpret_cast<void **>(&sl.hseg), seg_bytes,
                                  hipHostMallocDefault) == hipSuccess;
         ok = ok && hipMalloc(reinterpret_cast<void **>(&sl.dseg), seg_bytes) == hipSuccess;
     }
     if (!ok) {
         for (Slot &sl : s->slots) {
-            if (sl.dseg) hipFree(sl.dseg);
-            if (sl.hseg) hipHostFree(sl.hseg);
-            if (sl.done) hipEventDestroy(sl.done);
-            if (sl.stream) hipStreamDestroy(sl.stream);
+            if (sl.dseg) (void)hipFree(sl.dseg);
+            if (sl.hseg) (void)hipHostFree(sl.hseg);
+            for (hipEvent_t e : sl.ev)
+                if (e) (void)hipEventDestroy(e);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
-        hipFree(s->arena_dev);
+        (void)hipFree(s->arena_dev);
         return LBESSEL_EHIP;
     }
     s->stats.arena_bytes = s->cfg.arena_bytes;
@@ -489,15 +515,16 @@ int lbessel_server_destroy(lbessel_server_t *s) {
     s->cv_work.notify_all();
     if (s->worker.joinable())
         s->worker.join();
-    hipSetDevice(s->device);
+    (void)hipSetDevice(s->device);
     for (Slot &sl : s->slots) {
-        hipStreamSynchronize(sl.stream);
-        hipFree(sl.dseg);
-        hipHostFree(sl.hseg);
-        hipEventDestroy(sl.done);
-        hipStreamDestroy(sl.stream);
+        (void)hipStreamSynchronize(sl.stream);
+        (void)hipFree(sl.dseg);
+        (void)hipHostFree(sl.hseg);
+        for (hipEvent_t e : sl.ev)
+            (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(sl.stream);
     }
-    hipFree(s->arena_dev);
+    (void)hipFree(s->arena_dev);
     delete s;
     return LBESSEL_OK;
 }

@@ -28,12 +28,16 @@ import json
 import os
 import sys
 
-POINTS = [  # (kind, branch, v, x): well inside each branch's region
-    ("I", 0, 3.0, 40.0), ("I", 1, 40.0, 10.0), ("I", 2, 3.0, 5.0),
-    ("K", 0, 3.0, 40.0), ("K", 1, 40.0, 10.0),
+POINTS = [  # (kind, branch, v, x): well inside each branch's region; the Debye
+    # branch at one order per term-count tier (U_13, U_9, U_6, U_4)
+    ("I", 0, 3.0, 40.0), ("I", 1, 20.0, 10.0), ("I", 1, 40.0, 10.0), ("I", 1, 100.0, 10.0),
+    ("I", 1, 400.0, 10.0), ("I", 2, 3.0, 5.0),
+    ("K", 0, 3.0, 40.0), ("K", 1, 20.0, 10.0), ("K", 1, 40.0, 10.0), ("K", 1, 100.0, 10.0),
+    ("K", 1, 400.0, 10.0),
     ("K", 2, 3.0, 5.0), ("K", 2, 0.5, 1e-4), ("K", 2, 12.0, 0.01),
 ]
-NAMES = {0: "mu20", 1: "u13", 2: "fallback"}
+U_TIER_NAMES = {20.0: "u13", 40.0: "u9", 100.0: "u6", 400.0: "u4"}
+NAMES = {0: "mu20", 2: "fallback"}
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "opmodel.json")
 
 
@@ -78,6 +82,8 @@ def reduce(path: str, points_json: str) -> dict:
         per = disp[d]["SQ_INSTS_VALU"] / disp[d]["SQ_WAVES"]
         if (kind, b) == ("K", 2):
             fb.append((c, per, v0, x0))
+        elif b == 1:
+            model[f"{kind}_f64"][U_TIER_NAMES[v0]] = per
         else:
             model[f"{kind}_f64"][NAMES[b]] = per
     A = np.array([[1.0, c] for c, _, _, _ in fb])
