@@ -341,6 +341,69 @@ def order01_bench(lb, torch, n=20_000_000):
     return {"n": n, "results": res}
 
 
+# The paper's own runtime tables (RTX 2080 Ti, binary64; Sec. "Runtime",
+# Tables 6 and 7): milliseconds for 10M points per region (Table 6) and 100M
+# points at v = 0, 1 (Table 7).  Quoted as context beside this GPU's times on
+# the same workloads.
+PAPER_TABLE6_MS = {("I", "small"): 50.41, ("I", "large"): 39.68,
+                   ("K", "small"): 430.60, ("K", "large"): 39.96}
+PAPER_TABLE7_MS = {("I", 0, "small"): 433.00, ("I", 0, "large"): 187.14,
+                   ("I", 1, "small"): 336.44, ("I", 1, "large"): 175.59}
+
+
+def paper_tables_bench(lb, torch):
+    """The paper's runtime workloads on this GPU (binary64, inputs resident):
+    Table 6: 10M (v, x) pairs uniform in the Small [0,150]^2 and Large
+    [150,1e4]^2 ([150,4000]^2 for K) regions; Table 7: 100M x at v = 0 and 1
+    in the same x ranges, through the scalar-order entry points."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(20240918)
+
+    def timed(call):
+        call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    t6 = {}
+    n = 10_000_000
+    for kind in ("I", "K"):
+        for region, lo, hi in (("small", 0.0, 150.0),
+                               ("large", 150.0, 1e4 if kind == "I" else 4000.0)):
+            v = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64) * (hi - lo) + lo
+            x = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64) * (hi - lo) + lo
+            f = lb.log_iv if kind == "I" else lb.log_kv
+            ms = timed(lambda: f(v, x))
+            t6[f"{kind}:{region}"] = {"ms": ms, "G_evals_s": n / ms / 1e6,
+                                      "paper_ms_rtx2080ti": PAPER_TABLE6_MS[(kind, region)],
+                                      "ratio_vs_paper": PAPER_TABLE6_MS[(kind, region)] / ms}
+            del v, x
+    t7 = {}
+    n = 100_000_000
+    for region, lo, hi in (("small", 0.0, 150.0), ("large", 150.0, 1e4)):
+        x = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64) * (hi - lo) + lo
+        for order in (0, 1):
+            for kind in ("I", "K"):
+                f = lb.log_iv_order if kind == "I" else lb.log_kv_order
+                ms = timed(lambda: f(float(order), x))
+                row = {"ms": ms, "G_evals_s": n / ms / 1e6}
+                if kind == "I":
+                    row["paper_ms_rtx2080ti"] = PAPER_TABLE7_MS[("I", order, region)]
+                    row["ratio_vs_paper"] = row["paper_ms_rtx2080ti"] / ms
+                t7[f"{kind}{order}:{region}"] = row
+        del x
+    return {"table6_10M": t6, "table7_100M": t7,
+            "note": "paper times are the RTX 2080 Ti means of its Tables 6 and 7 (context)"}
+
+
 def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
     """Open-loop Poisson request stream through the native server: uneven
     evaluation requests (host arrays, 1 .. 4M pairs, I/K, f64/f32) and vMF
@@ -432,6 +495,8 @@ def main():
     ap.add_argument("--no-vmf", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-tables", action="store_true",
+                    help="skip the order-0/1 and paper runtime-table workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -540,7 +605,11 @@ def main():
     ablations = None
     if not args.no_ablation:
         ablations = ablation_bench(lb, torch, sets)
-    order01 = order01_bench(lb, torch)
+    order01, paper_tables = None, None
+    if not args.no_tables:
+        log("orders 0/1 and the paper's runtime tables")
+        order01 = order01_bench(lb, torch)
+        paper_tables = paper_tables_bench(lb, torch)
 
     vmf_res = None
     if not args.no_vmf:
@@ -588,6 +657,7 @@ def main():
         "grouping_ablation": ablation,
         "ablations": ablations,
         "order01": order01,
+        "paper_tables": paper_tables,
         "vmf": vmf_res,
         "serving": serving,
         "kernels": kern,
