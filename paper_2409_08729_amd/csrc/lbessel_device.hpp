@@ -476,21 +476,27 @@ __device__ __forceinline__ double br_k_tiny_x(double v, double x) {
 // are multiples of 1/64, so every t_j is exact and the only rounding in a
 // term is that of its own exponent.  The sum is kept relative to the
 // log-integrand at the grid point nearest t* (log-sum shift).
-// e^t at the grid nodes of br_k_cosh (t = i/64, 0 <= i < 4096) as e^{i>>6} e^{(i&63)/64},
-// indices clamped to the tables (a node beyond t = 64 only ever ends a walk);
-// two correctly rounded table entries and one product (<= 1.5 ulp).  The
-// tables are copied into LDS by the kernel (ktab_load) before any use.
+// e^t and e^-t at the grid nodes of br_k_cosh (t = i/64, 0 <= i < 4096) as
+// e^{+-(i>>6)} e^{+-(i&63)/64}, indices clamped to the tables (a node beyond
+// t = 64 only ever ends a walk); two correctly rounded table entries and one
+// product each (<= 1.5 ulp), so a node needs no division.  Each entry holds
+// the pair (e^+, e^-), read with one 16-byte LDS load.  The tables are copied
+// into LDS by the kernel (ktab_load) before any use.
 struct KTab {
-    double eint[64];
-    double efrac[64];
+    double2 eint[64];    // (e^n, e^-n)
+    double2 efrac[64];   // (e^{f/64}, e^{-f/64})
 };
 
 // Cooperative copy of the tables into LDS; every thread of the workgroup
 // must call it, before any evaluation of the K fallback.
 __device__ __forceinline__ void ktab_load(KTab *t) {
-    for (int i = threadIdx.x; i < 128; i += blockDim.x)
-        (i < 64 ? t->eint[i] : t->efrac[i - 64]) =
-            (i < 64) ? tables::kExpInt64[i] : tables::kExpFrac64[i - 64];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+        const int j = i & 63;
+        if (i < 64)
+            t->eint[j] = double2{tables::kExpInt64[j], tables::kExpNegInt64[j]};
+        else
+            t->efrac[j] = double2{tables::kExpFrac64[j], tables::kExpNegFrac64[j]};
+    }
     __syncthreads();
 }
 
@@ -562,8 +568,9 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
             // e^{|t|}: a walk from t0 may step past t = 0, where the even
             // integrand is evaluated at its mirror node
             const int aq = abs(iq);
-            const double e = kt->eint[min(aq >> 6, 63)] * kt->efrac[aq & 63];
-            const double a = fma(-0.5 * x, e + fm::rcp_nr(e), -M);
+            const double2 pi = kt->eint[min(aq >> 6, 63)];
+            const double2 pf = kt->efrac[aq & 63];
+            const double a = fma(-0.5 * x, pi.x * pf.x + pi.y * pf.y, -M);
             const double ap = fma(v, tj, a);
             const double ep = fm::exp64_bounded(ap);
             const double f = fma(ep, r, ep);

@@ -365,16 +365,20 @@ def render_header() -> str:
             lines.append("    {" + ", ".join(fmt(conv(c)) for c in row) + "},")
         lines.append("};")
     from decimal import Decimal, localcontext
-    # e^n and e^{f/64}: e^{t} for t a multiple of 1/64 in [0, 64) as one product
+    # e^{+-n} and e^{+-f/64}: e^{t} and e^{-t} for t a multiple of 1/64 in
+    # [0, 64) as one product each
     with localcontext() as ctx:
         ctx.prec = 50
         eint = [Decimal(n).exp() for n in range(64)]
         efrac = [(Decimal(f) / 64).exp() for f in range(64)]
-    lines.append("// e^n, n = 0..63, and e^{f/64}, f = 0..63 (K fallback grid nodes).")
-    lines.append("__constant__ const double kExpInt64[64] = {"
-                 + ", ".join(f64_hex(dec_to_f64(d)) for d in eint) + "};")
-    lines.append("__constant__ const double kExpFrac64[64] = {"
-                 + ", ".join(f64_hex(dec_to_f64(d)) for d in efrac) + "};")
+        enint = [(-Decimal(n)).exp() for n in range(64)]
+        enfrac = [(-Decimal(f) / 64).exp() for f in range(64)]
+    lines.append("// e^n, n = 0..63, and e^{f/64}, f = 0..63 (K fallback grid nodes),")
+    lines.append("// and their reciprocals e^-n, e^{-f/64}.")
+    for name, vals in (("kExpInt64", eint), ("kExpFrac64", efrac),
+                       ("kExpNegInt64", enint), ("kExpNegFrac64", enfrac)):
+        lines.append(f"__constant__ const double {name}[64] = {{"
+                     + ", ".join(f64_hex(dec_to_f64(d)) for d in vals) + "};")
     lines.append(f"constexpr double kEulerGamma64 = {f64_hex(dec_to_f64(Decimal(EULER_GAMMA_50)))};")
     lines.append(f"constexpr float kEulerGamma32 = {f32_hex(dec_to_f32(Decimal(EULER_GAMMA_50)))};")
     lines.append("")

@@ -155,3 +155,27 @@ def test_order01_series_tables():
     head = sum(cc * q ** k for k, cc in enumerate(s0))
     nxt = q ** len(s0) / math.factorial(len(s0)) ** 2
     assert nxt / head < Fraction(1, 2 ** 60)
+
+
+def _header_array(text: str, name: str) -> list[float]:
+    import re
+    m = re.search(name + r"\[64\] = \{([^}]*)\};", text)
+    assert m, name
+    return [float.fromhex(t.strip()) for t in m.group(1).split(",")]
+
+
+def test_exp_grid_tables():
+    """e^{+-n} and e^{+-f/64} for the K fallback nodes: each entry within one
+    ulp of the C library's exp, e^1 the nearest double to e, and every
+    product e^a e^-a within two ulps of 1."""
+    text = gt.render_header()
+    ei, ef = _header_array(text, "kExpInt64"), _header_array(text, "kExpFrac64")
+    ni, nf = _header_array(text, "kExpNegInt64"), _header_array(text, "kExpNegFrac64")
+    assert ei[0] == ef[0] == ni[0] == nf[0] == 1.0
+    assert ei[1] == math.e
+    for k in range(64):
+        for tab, arg in ((ei, k), (ef, k / 64), (ni, -k), (nf, -k / 64)):
+            ref = math.exp(arg)
+            assert abs(tab[k] - ref) <= math.ulp(ref), (k, arg)
+        assert abs(ei[k] * ni[k] - 1.0) <= 2 * 2 ** -52
+        assert abs(ef[k] * nf[k] - 1.0) <= 2 * 2 ** -52
