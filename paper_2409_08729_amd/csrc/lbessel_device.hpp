@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbessel_fastmath.hpp"
 #include "lbessel_tables.h"
 
@@ -296,8 +298,39 @@ __device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
 // first term cannot overflow.  The sum stops once the current ratio is below
 // 1/2 (all later ones are smaller) and the term is below eps * sum, which
 // bounds the dropped tail by 2 eps relative.
+// log Gamma(1 + v) for 0 <= v <= 15 in binary64 (the prefactor of the I
+// series): on v in [j/2, (j+1)/2] a degree-15 polynomial in u = 4v - 2j - 1
+// (a truncated Chebyshev interpolant in monomial form, absolute error below
+// ~2e-16), read from a table in LDS.  Branch-free, so the lanes of a wave
+// run the same instructions whatever their orders; the library lgamma
+// branches by argument range.  The table is copied into LDS by the kernel
+// (lgtab_load) before any use.
+struct LgTab {
+    double c[tables::kLgIntervals][tables::kLgCoefs];
+};
+
+// Cooperative copy of the table into LDS; every thread of the workgroup must
+// call it, before any evaluation of the I series.
+__device__ __forceinline__ void lgtab_load(LgTab *t) {
+    constexpr int n = tables::kLgIntervals * tables::kLgCoefs;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        (&t->c[0][0])[i] = (&tables::kLgamma1p64[0][0])[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double lgamma1p_tab(double v, const LgTab *t) {
+    const int j = min(int(2.0 * v), tables::kLgIntervals - 1);
+    const double u = fma(4.0, v, -double(2 * j + 1));
+    const double *c = t->c[j];
+    double s = c[tables::kLgCoefs - 1];
+#pragma unroll
+    for (int i = tables::kLgCoefs - 2; i >= 0; --i)
+        s = fma(s, u, c[i]);
+    return s;
+}
+
 template <typename T>
-__device__ __forceinline__ T br_series_i(T v, T x) {
+__device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     const T hx = T(0.5) * x;
     const T q = hx * hx;
     T term = T(1);
@@ -310,8 +343,17 @@ __device__ __forceinline__ T br_series_i(T v, T x) {
         if (den > T(2) * q && term < Cst<T>::series_eps * sum)
             break;
     }
+    T lg;
+    if constexpr (std::is_same<T, double>::value) {
+        if (v <= 15.0)
+            lg = lgamma1p_tab(v, lt);
+        else
+            lg = lgamma(v + 1.0);
+    } else {
+        lg = lgamma(v + T(1));
+    }
     // log(x/2) as log x - log 2: x/2 can underflow for subnormal x
-    return v * (llog(x) - Cst<T>::ln2) - lgamma(v + T(1)) + llog(sum);
+    return v * (llog(x) - Cst<T>::ln2) - lg + llog(sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -499,6 +541,11 @@ __device__ __forceinline__ void ktab_load(KTab *t) {
     }
     __syncthreads();
 }
+
+// The fallback's LDS tables by kind: e^{+-t} for K, log Gamma(1 + v) for I.
+template <int KIND> struct FbTabSel { using type = KTab; };
+template <> struct FbTabSel<KIND_I> { using type = LgTab; };
+template <int KIND> using FbTab = typename FbTabSel<KIND>::type;
 
 // nodes (may be null): receives the number of integrand evaluations.
 __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
@@ -721,7 +768,7 @@ __device__ __forceinline__ T order01(T x) {
 // cosh-integral trapezoid for x >= 1e-10; below, the two-term small-argument
 // form (v < 0.3) or the 600-node rule on the u-integral of the paper.
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
-__device__ __forceinline__ T eval_branch(int b, T v, T x, const KTab *kt) {
+__device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND> *kt) {
     if (VAR == VAR_SEVEN) {
         switch (b) {
         case B7_MU3: return br_mu<T, KIND, 3>(v, x);
@@ -742,8 +789,9 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const KTab *kt) {
         }
         return br_u<T, KIND>(v, x);
     }
-    if (KIND == KIND_I)
-        return br_series_i<T>(v, x);
+    if constexpr (KIND == KIND_I) {
+        return br_series_i<T>(v, x, kt);
+    } else {
     constexpr bool u_integral = (VAR == VAR_U_INTEGRAL || VAR == VAR_SIMPSON || VAR == VAR_PAPER);
     if (!u_integral && x >= T(1e-10))
         return T(br_k_cosh(double(v), double(x), kt));
@@ -752,6 +800,7 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const KTab *kt) {
     if (VAR == VAR_SIMPSON || VAR == VAR_PAPER)
         return br_quad_k<T, double, true>(v, x);
     return br_quad_k<T, double>(v, x);
+    }
 }
 
 

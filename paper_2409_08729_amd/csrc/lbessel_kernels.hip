@@ -110,21 +110,35 @@ __device__ __forceinline__ T combine(T v, T x, T g, T p, T y0, T y1) {
 
 // One evaluation that may still hit a special value (the v + 1 order).
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
-__device__ __forceinline__ T eval_full(T v, T x, const KTab *kt) {
+__device__ __forceinline__ T eval_full(T v, T x, const FbTab<KIND> *kt) {
     T y;
     if (special_value<T, KIND>(v, x, &y))
         return y;
     return eval_branch<T, KIND, VAR>(classify_var<T, KIND, VAR>(v, x), v, x, kt);
 }
 
-// LDS copy of the K fallback's exp tables, loaded by every workgroup of a K
-// kernel before its first evaluation (all threads must reach the call).
+// LDS copy of the fallback's tables (K: e^{+-t}; I: log Gamma(1 + v)), loaded
+// by every workgroup before its first evaluation (all threads must reach the
+// call).
 template <int KIND>
-__device__ __forceinline__ const KTab *ktab_for_kind() {
-    __shared__ KTab kt;
-    if (KIND == KIND_K)
-        ktab_load(&kt);
+__device__ __forceinline__ FbTab<KIND> *fb_tab_storage() {
+    __shared__ FbTab<KIND> kt;
     return &kt;
+}
+
+template <int KIND>
+__device__ __forceinline__ void fb_tab_load(FbTab<KIND> *kt) {
+    if constexpr (KIND == KIND_K)
+        ktab_load(kt);
+    else
+        lgtab_load(kt);
+}
+
+template <int KIND>
+__device__ __forceinline__ const FbTab<KIND> *ktab_for_kind() {
+    FbTab<KIND> *kt = fb_tab_storage<KIND>();
+    fb_tab_load<KIND>(kt);
+    return kt;
 }
 
 // ---------------------------------------------------------------------------
@@ -132,7 +146,7 @@ __device__ __forceinline__ const KTab *ktab_for_kind() {
 // ---------------------------------------------------------------------------
 template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
-    const KTab *kt = ktab_for_kind<KIND>();
+    const auto *kt = ktab_for_kind<KIND>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= a.n)
         return;
@@ -224,7 +238,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     constexpr bool STAGE = (NV == 1) && (KIND == KIND_K);
     __shared__ Smem<T, NV, NC, STAGE> sm;
 
-    const KTab *kt = ktab_for_kind<KIND>();
+    // the fallback's tables, loaded below only if the tile has fallback work
+    FbTab<KIND> *kt = fb_tab_storage<KIND>();
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -350,6 +365,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     const int n_fb = sm.n_fb;                     // all fallback buckets
     const int n_fb_u = sm.n_fb_u;                 // ... plus Debye
     const int n_all = sm.n_all;
+    if (n_fb > 0)                                 // workgroup-uniform
+        fb_tab_load<KIND>(kt);
 
     // Uniform tile (one class only, e.g. one order whose arguments all fall
     // in one regime): every wave already runs one branch, so each thread
@@ -479,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_sorted_eval(const uint8_t *__restr
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ x,
                                                           double *__restrict__ out, int64_t n) {
-    const KTab *kt = ktab_for_kind<KIND>();
+    const auto *kt = ktab_for_kind<KIND>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
@@ -577,7 +594,7 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_branch(int b, const double *v, const double *x,
                                                      double *out, int64_t n) {
-    const KTab *kt = ktab_for_kind<KIND>();
+    const auto *kt = ktab_for_kind<KIND>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;

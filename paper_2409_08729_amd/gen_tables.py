@@ -27,6 +27,7 @@ Run as a script it writes ``csrc/lbessel_tables.h``.
 """
 from __future__ import annotations
 
+import functools
 import math
 import os
 from fractions import Fraction
@@ -271,6 +272,89 @@ def k01_chebyshev(v: int, deg: int = CHEB01_DEG, prec: int = 100):
         return cs
 
 
+# ----------------------------------------------------------------------------
+# log Gamma(1 + v) on 0 <= v <= 15 (prefactor of the I series, binary64)
+# ----------------------------------------------------------------------------
+LG_INTERVALS = 30    # half-unit intervals [j/2, (j+1)/2] of v
+LG_DEG = 15          # polynomial degree on each interval
+LG_NODES = 32        # Chebyshev points of the interpolant that is truncated
+
+
+@functools.lru_cache(maxsize=None)
+def bernoulli_numbers(n: int) -> tuple[Fraction, ...]:
+    """B_0 .. B_n (B_1 = +1/2) by the Akiyama-Tanigawa recurrence."""
+    a = [Fraction(0)] * (n + 1)
+    out = []
+    for m in range(n + 1):
+        a[m] = Fraction(1, m + 1)
+        for j in range(m, 0, -1):
+            a[j - 1] = j * (a[j - 1] - a[j])
+        out.append(a[0])
+    return tuple(out)
+
+
+def dec_lgamma(z, prec: int = 40):
+    """log Gamma(z) for z > 0 in `prec`-digit decimals: shift to w = z + m >= 40
+    by Gamma(z) = Gamma(w) / (z (z+1) ... (w-1)), then Stirling's series with
+    20 terms (DLMF 5.11.1; remainder below the first omitted term, ~1e-51)."""
+    from decimal import Decimal, localcontext
+    bern = bernoulli_numbers(40)
+    with localcontext() as ctx:
+        ctx.prec = prec + 15
+        z = Decimal(z)
+        prod = Decimal(1)
+        w = z
+        while w < 40:
+            prod *= w
+            w += 1
+        half_log_2pi = (2 * Decimal(PI_50)).ln() / 2
+        acc = (w - Decimal("0.5")) * w.ln() - w + half_log_2pi
+        wp = w
+        for k in range(1, 21):
+            b = bern[2 * k]
+            acc += Decimal(b.numerator) / Decimal(b.denominator) / (2 * k * (2 * k - 1) * wp)
+            wp *= w * w
+        res = acc - prod.ln()
+    with localcontext() as ctx:
+        ctx.prec = prec
+        return +res
+
+
+def lgamma1p_poly(j: int, deg: int = LG_DEG, nodes: int = LG_NODES, prec: int = 32):
+    """Monomial coefficients a_0..a_deg in u of the degree-`deg` truncation of the
+    Chebyshev interpolant (at `nodes` points) of log Gamma(1 + v) on the
+    interval v = (2j + 1 + u)/4, u in [-1, 1]."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec + 10
+        pi = Decimal(PI_50)
+        us = [_dec_cos(pi * (Decimal(k) + Decimal("0.5")) / nodes, prec + 10)
+              for k in range(nodes)]
+        gs = [dec_lgamma(1 + (2 * j + 1 + u) / 4, prec + 10) for u in us]
+        # T_m(u_k) by the three-term recurrence
+        tk = [[Decimal(1)] * nodes, list(us)]
+        for m in range(2, deg + 1):
+            tk.append([2 * us[k] * tk[m - 1][k] - tk[m - 2][k] for k in range(nodes)])
+        cs = []
+        for m in range(deg + 1):
+            c = sum(gs[k] * tk[m][k] for k in range(nodes)) * 2 / nodes
+            cs.append(c / 2 if m == 0 else c)
+        # monomial form: T_0 = 1, T_1 = u, T_{m+1} = 2 u T_m - T_{m-1}
+        tpoly = [[Decimal(1)], [Decimal(0), Decimal(1)]]
+        for m in range(2, deg + 1):
+            nxt = [Decimal(0)] * (m + 1)
+            for i, c in enumerate(tpoly[m - 1]):
+                nxt[i + 1] += 2 * c
+            for i, c in enumerate(tpoly[m - 2]):
+                nxt[i] -= c
+            tpoly.append(nxt)
+        a = [Decimal(0)] * (deg + 1)
+        for m in range(deg + 1):
+            for i, c in enumerate(tpoly[m]):
+                a[i] += cs[m] * c
+        return a
+
+
 def _debye_arrays():
     polys = debye_polys(U_TERMS)
     rows = [debye_p_coeffs(k, polys) for k in range(1, U_TERMS + 1)]
@@ -379,6 +463,15 @@ def render_header() -> str:
                        ("kExpNegInt64", enint), ("kExpNegFrac64", enfrac)):
         lines.append(f"__constant__ const double {name}[64] = {{"
                      + ", ".join(f64_hex(dec_to_f64(d)) for d in vals) + "};")
+    lines.append(f"// log Gamma(1 + v), 0 <= v <= {LG_INTERVALS // 2}: on v in [j/2, (j+1)/2] the "
+                 f"polynomial sum_i a[j][i] u^i,")
+    lines.append("// u = 4 v - 2 j - 1 in [-1, 1] (truncated Chebyshev interpolant, monomial form).")
+    lines.append(f"constexpr int kLgIntervals = {LG_INTERVALS};")
+    lines.append(f"constexpr int kLgCoefs = {LG_DEG + 1};")
+    lines.append(f"__constant__ const double kLgamma1p64[{LG_INTERVALS}][{LG_DEG + 1}] = {{")
+    for j in range(LG_INTERVALS):
+        lines.append("    {" + ", ".join(f64_hex(dec_to_f64(c)) for c in lgamma1p_poly(j)) + "},")
+    lines.append("};")
     lines.append(f"constexpr double kEulerGamma64 = {f64_hex(dec_to_f64(Decimal(EULER_GAMMA_50)))};")
     lines.append(f"constexpr float kEulerGamma32 = {f32_hex(dec_to_f32(Decimal(EULER_GAMMA_50)))};")
     lines.append("")

@@ -179,3 +179,56 @@ def test_exp_grid_tables():
             assert abs(tab[k] - ref) <= math.ulp(ref), (k, arg)
         assert abs(ei[k] * ni[k] - 1.0) <= 2 * 2 ** -52
         assert abs(ef[k] * nf[k] - 1.0) <= 2 * 2 ** -52
+
+
+def test_bernoulli_numbers():
+    b = gt.bernoulli_numbers(20)
+    assert b[0] == 1 and b[1] == Fraction(1, 2) and b[2] == Fraction(1, 6)
+    assert b[4] == Fraction(-1, 30) and b[12] == Fraction(-691, 2730)
+    assert b[20] == Fraction(-174611, 330) and all(b[k] == 0 for k in range(3, 21, 2))
+
+
+def test_decimal_lgamma_closed_forms():
+    """log Gamma at integers (log (n-1)!) and at 1/2 (log sqrt(pi))."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    for n in (1, 2, 3, 7, 16, 41, 60):
+        ref = Decimal(math.factorial(n - 1)).ln()
+        assert abs(gt.dec_lgamma(Decimal(n)) - ref) < Decimal(10) ** -35, n
+    half = Decimal(gt.PI_50).sqrt().ln()
+    assert abs(gt.dec_lgamma(Decimal("0.5")) - half) < Decimal(10) ** -35
+
+
+def test_lgamma1p_table():
+    """The binary64 polynomials of log Gamma(1 + v), evaluated by Horner as the
+    kernel does, against the C library's lgamma on a grid over [0, 15], and
+    zero at v = 0 and v = 1 (Gamma(1) = Gamma(2) = 1)."""
+    text = gt.render_header()
+    import re
+    m = re.search(r"kLgamma1p64\[(\d+)\]\[(\d+)\] = \{(.*?)\n\};", text, re.S)
+    nint, ncoef = int(m.group(1)), int(m.group(2))
+    rows = [[float.fromhex(t.strip()) for t in row.split(",") if t.strip()]
+            for row in re.findall(r"\{([^{}]*)\}", m.group(3))]
+    assert len(rows) == nint == 30 and all(len(r) == ncoef for r in rows)
+
+    def lg(v):
+        j = min(int(2.0 * v), nint - 1)
+        u = 4.0 * v - (2 * j + 1)
+        s = rows[j][-1]
+        for c in reversed(rows[j][:-1]):
+            s = s * u + c
+        return s
+
+    assert abs(lg(0.0)) < 5e-17 and abs(lg(1.0)) < 1e-16
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    worst, worst_libm = 0.0, 0.0
+    for v in np.linspace(0.0, 15.0, 1201):
+        exact = gt.dec_lgamma(1 + Decimal(float(v)))
+        scale = max(1.0, abs(float(exact)))
+        worst = max(worst, float(abs(Decimal(lg(v)) - exact)) / scale)
+        worst_libm = max(worst_libm, abs(lg(v) - math.lgamma(1.0 + v)) / scale)
+    # the decimal log Gamma is pinned above; the C library's lgamma is only
+    # good to ~1e-15 near its minimum, hence the looser second bound
+    assert worst < 4e-16, worst
+    assert worst_libm < 2e-15, worst_libm
