@@ -76,6 +76,7 @@ template <> struct Cst<double> {
     static constexpr double series_eps = 0x1p-56;  // relative truncation
     static constexpr double big_z = 1e150;         // sqrt(1+z^2) == z beyond
     static constexpr double tiny_z = 1e-290;       // x/v may have lost bits below
+    static constexpr double safe_big = 1e300;      // 1/a and products stay normal below
 };
 template <> struct Cst<float> {
     static constexpr float log_2pi = 0x1.d67f1cp+0f;
@@ -87,6 +88,7 @@ template <> struct Cst<float> {
     static constexpr float series_eps = 0x1p-27f;
     static constexpr float big_z = 1e18f;
     static constexpr float tiny_z = 1e-30f;
+    static constexpr float safe_big = 1e36f;
 };
 
 // Regime thresholds.  Shapes of Table 1:
@@ -214,10 +216,37 @@ template <> __device__ __forceinline__ const float (*hankel_table<float>())[2] {
 
 // NT correction terms (mu_NT); the library uses NT = 20, the seven-branch
 // variant of Algorithm 1 also mu_3.
-template <typename T, int KIND, int NT = tables::kMuTerms>
-__device__ __forceinline__ T br_mu(T v, T x) {
+// x at least safe_big: a division and two logarithms, every intermediate in range.
+template <typename T, int KIND, int NT>
+__device__ __forceinline__ T br_mu_wide(T v, T x) {
     const T mu = T(4) * v * v;
     const T q = (KIND == KIND_I ? T(-0.125) : T(0.125)) / x;
+    const LB_CONST_AS T *hk = opaque_const<T>(&hankel_table<T>()[0][0]);
+    T c = T(1);
+    T s = T(0);
+#pragma unroll
+    for (int k = 1; k <= NT; ++k) {
+        const T d = (mu - hk[2 * (k - 1) + 1]) * hk[2 * (k - 1)];
+        c = c * d * q;
+        s = s + c;
+    }
+    const T ls = llog(fabs(T(1) + s));
+    if (KIND == KIND_I)
+        return x - T(0.5) * (Cst<T>::log_2pi + llog(x)) + ls;
+    else
+        return T(0.5) * (Cst<T>::log_pi_2 - llog(x)) - x + ls;
+}
+
+// Below safe_big 1/x is a normal number: one reciprocal serves the series and
+// the prefactor, and log|1 + s| - log(x)/2 is taken as one logarithm,
+// log((1 + s)^2 / x) / 2.
+template <typename T, int KIND, int NT = tables::kMuTerms>
+__device__ __forceinline__ T br_mu(T v, T x) {
+    if (!(x < Cst<T>::safe_big))
+        return br_mu_wide<T, KIND, NT>(v, x);
+    const T mu = T(4) * v * v;
+    const T ix = lrcp(x);
+    const T q = (KIND == KIND_I ? T(-0.125) : T(0.125)) * ix;
     const LB_CONST_AS T *hk = opaque_const<T>(&hankel_table<T>()[0][0]);
     T c = T(1);
     T s = T(0);
@@ -229,11 +258,12 @@ __device__ __forceinline__ T br_mu(T v, T x) {
         c = c * d * q;
         s = s + c;
     }
-    const T ls = llog(fabs(T(1) + s));
+    const T s1 = fabs(T(1) + s);
+    const T lq = llog(s1 * s1 * ix);
     if (KIND == KIND_I)
-        return x - T(0.5) * (Cst<T>::log_2pi + llog(x)) + ls;
+        return x - T(0.5) * Cst<T>::log_2pi + T(0.5) * lq;
     else
-        return T(0.5) * (Cst<T>::log_pi_2 - llog(x)) - x + ls;
+        return T(0.5) * (Cst<T>::log_pi_2 + lq) - x;
 }
 
 // ---------------------------------------------------------------------------
@@ -253,11 +283,13 @@ template <> __device__ __forceinline__ const float (*debye_table<float>())[14] {
 
 // NT Debye terms (U_NT); the library uses NT = 13, the seven-branch variant
 // of Algorithm 1 also U_4, U_6 and U_9.
-template <typename T, int KIND, int NT = tables::kUTerms>
+// Arguments up to the end of the range (v or x at least safe_big): divisions
+// and three logarithms, every intermediate in range.
+template <typename T, int KIND, int NT>
 // nt (<= NT, runtime): terms actually summed.  Terms above nt are skipped
 // per lane, so lanes of one wave with different nt cost the largest nt once,
 // and a term count gives the same bits whichever way it is reached.
-__device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
+__device__ __forceinline__ T br_u_wide(T v, T x, int nt) {
     const T z = x / v;
     const T r = (z < Cst<T>::big_z) ? sqrt(fma(z, z, T(1))) : z;
     const T t = T(1) / r;
@@ -287,6 +319,54 @@ __device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
         return v * eta - T(0.5) * (Cst<T>::log_2pi + lvr) + ls;
     else
         return T(0.5) * (Cst<T>::log_pi_2 - lvr) - v * eta + ls;
+}
+
+// Below safe_big every reciprocal and product below is a normal number:
+// x/v and z/(1 + r) by a reciprocal and one correction step (~0.5 ulp, they
+// enter v eta), 1/r and 1/v by reciprocals, and log|1 + acc| - log(v r)/2 as
+// one logarithm, log((1 + acc)^2 / (v r)) / 2.
+template <typename T, int KIND, int NT = tables::kUTerms>
+// nt (<= NT, runtime): terms actually summed.  Terms above nt are skipped
+// per lane, so lanes of one wave with different nt cost the largest nt once,
+// and a term count gives the same bits whichever way it is reached.
+__device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
+    if (!(v < Cst<T>::safe_big && x < Cst<T>::safe_big))
+        return br_u_wide<T, KIND, NT>(v, x, nt);
+    const T iv = lrcp(v);
+    T z = x * iv;
+    z = fma(fma(-z, v, x), iv, z);
+    const T r = (z < Cst<T>::big_z) ? sqrt(fma(z, z, T(1))) : z;
+    const T t = lrcp(r);
+    const T p = t * t;
+    const T w = (KIND == KIND_I ? t : -t) * iv;
+    const LB_CONST_AS T *P = opaque_const<T>(&debye_table<T>()[0][0]);
+    T acc = T(0);
+#pragma unroll
+    for (int k = NT; k >= 1; --k) {
+        if (k > nt)
+            continue;
+        const LB_CONST_AS T *row = P + 14 * (k - 1);
+        T pk = fm::fma_c(row[k], p, row[k - 1]);
+#pragma unroll
+        for (int j = k - 2; j >= 0; --j)
+            pk = fm::fma_c(pk, p, row[j]);
+        acc = w * (pk + acc);
+    }
+    const T d = T(1) + r;
+    const T id = lrcp(d);
+    T zq = z * id;
+    zq = fma(fma(-zq, d, z), id, zq);
+    // z below the normal range (x/v < ~1e-290 in f64): log z from log x - log v
+    T lz = llog(zq);
+    if (z < Cst<T>::tiny_z)
+        lz = llog(x) - llog(v) - llog(d);
+    const T eta = r + lz;
+    const T s1 = fabs(T(1) + acc);
+    const T lq = llog(s1 * s1 * (t * iv));
+    if (KIND == KIND_I)
+        return v * eta - T(0.5) * Cst<T>::log_2pi + T(0.5) * lq;
+    else
+        return T(0.5) * (Cst<T>::log_pi_2 + lq) - v * eta;
 }
 
 // ---------------------------------------------------------------------------
