@@ -248,17 +248,17 @@ __device__ __forceinline__ T br_mu(T v, T x) {
     const T ix = lrcp(x);
     const T q = (KIND == KIND_I ? T(-0.125) : T(0.125)) * ix;
     const LB_CONST_AS T *hk = opaque_const<T>(&hankel_table<T>()[0][0]);
-    T c = T(1);
-    T s = T(0);
+    // 1 + s = 1 + t_1 (1 + t_2 (1 + ... (1 + t_NT))), t_k = c_k / c_{k-1} =
+    // (mu - (2k-1)^2) (1/k) q, by Horner from the last term (both constants are
+    // scalar operands); mu - (2k-1)^2 is exact, so at a half-integer order the
+    // vanishing factor still ends the sum exactly
+    T acc = T(1);
 #pragma unroll
-    for (int k = 1; k <= NT; ++k) {
-        // c_k = c_{k-1} * ((mu - (2k-1)^2) * (1/k)) * q; both constants are
-        // scalar operands of the add and the multiply
-        const T d = (mu - hk[2 * (k - 1) + 1]) * hk[2 * (k - 1)];
-        c = c * d * q;
-        s = s + c;
+    for (int k = NT; k >= 1; --k) {
+        const T t = (mu - hk[2 * (k - 1) + 1]) * (hk[2 * (k - 1)] * q);
+        acc = fma(t, acc, T(1));
     }
-    const T s1 = fabs(T(1) + s);
+    const T s1 = fabs(acc);
     const T lq = llog(s1 * s1 * ix);
     if (KIND == KIND_I)
         return x - T(0.5) * Cst<T>::log_2pi + T(0.5) * lq;
