@@ -438,7 +438,7 @@ def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
         else:
             base.append({"type": "vmf", "X": feats[r["p"]][: r["N"]], "result": results[i]})
     pairs = sum(r["n"] for r in reqs if r["type"] == "eval")
-    modes = (("batched", "batched", 4), ("plain", "plain", 1), ("plain_4streams", "plain", 4))
+    modes = (("batched", "batched", 8), ("plain", "plain", 1), ("plain_8streams", "plain", 8))
 
     def run(label, times):
         _, mode, streams = [m for m in modes if m[0] == label][0]
@@ -479,9 +479,9 @@ def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
                    "in/out; vMF (1/8 of requests): p in {2048, 8192, 32768}, N log-uniform "
                    "[1e3, 5e4], features on the device",
             "modes": {"batched": "FIFO memory admission, continuous batching into segmented "
-                                 "launches, 4 batches in flight",
+                                 "launches of up to 2^18 pairs, 8 batches in flight",
                       "plain": "same queue, one request at a time, one launch per request",
-                      "plain_4streams": "one launch per request, 4 requests in flight"},
+                      "plain_8streams": "one launch per request, 8 requests in flight"},
             "saturation": sat, "sweep": sweep}
 
 

@@ -106,8 +106,11 @@ typedef struct lbessel_server_stats {
     int64_t max_batch_requests_seen;
 } lbessel_server_stats_t;
 
-/* Default configuration: 2 GiB arena, 4 streams, batched, 64 requests and
- * 2^22 pairs per batch, spinning scheduler. */
+/* Default configuration: 2 GiB arena, 8 streams, batched, 64 requests and
+ * 2^18 pairs per batch, spinning scheduler.  With host-resident requests the
+ * server is bound by the copies: small batches keep a request from waiting
+ * long for its batch-mates' inputs, while the many small requests still
+ * share launches. */
 void lbessel_server_default_config(lbessel_server_config_t *cfg);
 
 /*

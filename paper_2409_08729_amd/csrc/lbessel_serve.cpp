@@ -385,10 +385,10 @@ void lbessel_server_default_config(lbessel_server_config_t *cfg) {
     if (cfg == nullptr)
         return;
     cfg->arena_bytes = int64_t(2) << 30;
-    cfg->streams = 4;
+    cfg->streams = 8;
     cfg->mode = LBESSEL_SERVE_BATCHED;
     cfg->max_batch_requests = 64;
-    cfg->max_batch_elems = int64_t(1) << 22;
+    cfg->max_batch_elems = int64_t(1) << 18;
     cfg->poll_us = 0;
 }
 
