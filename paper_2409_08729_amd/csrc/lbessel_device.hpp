@@ -641,43 +641,50 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     // right of t* it decreases monotonically, from the left (where psi' > 0)
     // its first step lands right of t*; where psi' <= 0 it restarts from the
     // bound asinh(v/x).  t0 is rounded to the 1/64 grid, so |dt| < 4e-3 ends it.
-    double t = 0.0;
+    // The peak and the step only place the grid, so they are computed in
+    // binary32 with hardware approximations; the shift, every term, both sums
+    // and the result are binary64 (x >= 1e-10 and v <= ~15 here, so every
+    // binary32 quantity below is in range).
+    const float vf = float(v), xf = float(x);
+    float t = 0.0f;
     if (v * v > x) {
-        const double q = v / x;
-        const double R = v * q;
-        auto asinh_pos = [](double a) { return fm::log64(a + sqrt(fma(a, a, 1.0))); };
-        const double tu = asinh_pos(q);
-        double ts = asinh_pos(R);
+        const float q = vf * fm::rcp_hw(xf);
+        const float R = vf * q;
+        auto asinh_pos = [](float a) { return fm::log_hw(a + fm::sqrt_hw(fmaf(a, a, 1.0f))); };
+        const float tu = asinh_pos(q);
+        float ts = asinh_pos(R);
         ts = asinh_pos(R * ts);
         ts = asinh_pos(R * ts);
-        t = fmin(tu, ts);
+        t = fminf(tu, ts);
         for (int it = 0; it < 16; ++it) {
-            const double e = fm::exp64(t), r = fm::rcp_nr(e);
-            const double z = fm::exp64(-2.0 * v * t);
-            const double iz = fm::rcp_nr(1.0 + z);
-            const double psi = fma(0.5 * x, e - r, -v * (1.0 - z) * iz);
-            const double dpsi = fma(0.5 * x, e + r, -4.0 * v * v * z * iz * iz);
-            if (!(dpsi > 0.0)) {   // left of psi's minimum
+            const float e = fm::exp_hw(t), r = fm::rcp_hw(e);
+            const float z = fm::exp_hw(-2.0f * vf * t);
+            const float iz = fm::rcp_hw(1.0f + z);
+            const float psi = fmaf(0.5f * xf, e - r, -vf * (1.0f - z) * iz);
+            const float dpsi = fmaf(0.5f * xf, e + r, -4.0f * vf * vf * z * iz * iz);
+            if (!(dpsi > 0.0f)) {   // left of psi's minimum
                 t = tu;
                 continue;
             }
-            const double dt = psi * fm::rcp_nr(dpsi);
-            t = fmax(t - dt, 0.0);
-            if (fabs(dt) < 4e-3)
+            const float dt = psi * fm::rcp_hw(dpsi);
+            t = fmaxf(t - dt, 0.0f);
+            if (fabsf(dt) < 4e-3f)
                 break;
         }
     }
-    const double et = fm::exp64(t);
-    const double ch = 0.5 * (et + fm::rcp_nr(et));
-    const int hq = max(int(floor(fmin(0.22 / fma(0.05, v, 1.0), 0.5 / sqrt(x * ch)) * 64.0)), 1);
-    const int t0q = int(rint(t * 64.0));
+    const float et = fm::exp_hw(t);
+    const float ch = 0.5f * (et + fm::rcp_hw(et));
+    const float hf = fminf(0.22f * fm::rcp_hw(fmaf(0.05f, vf, 1.0f)), 0.5f * fm::rsqrt_hw(xf * ch));
+    const int hq = max(int(floorf(hf * 64.0f)), 1);
+    const int t0q = int(rintf(t * 64.0f));
     const double h = hq * kGrid;
-    const double t0 = t0q * kGrid;
-    // shift M = log-integrand at t0 (log cosh(vt) = vt + log1p(e^{-2vt}) - ln 2)
-    const double e0 = fm::exp64(t0);
-    const double vt0 = v * t0;
-    const double M = fma(-0.5 * x, e0 + fm::rcp_nr(e0), vt0) +
-                     fm::log64(1.0 + fm::exp64(-2.0 * vt0)) - Cst<double>::ln2;
+    // shift M = log-integrand at t0 = t0q/64 in binary64 (log cosh(vt) =
+    // vt + log1p(e^{-2vt}) - ln 2), e^{+-t0} from the node tables
+    const double2 pi0 = kt->eint[min(t0q >> 6, 63)];
+    const double2 pf0 = kt->efrac[t0q & 63];
+    const double vt0 = v * (t0q * kGrid);
+    const double M = fma(-0.5 * x, pi0.x * pf0.x + pi0.y * pf0.y, vt0) +
+                     fm::log64(1.0 + fm::exp64_bounded(-2.0 * vt0)) - Cst<double>::ln2;
     // One walk over nodes i = i0 + j*di (units of 1/64), j = j0, j0+1, ...:
     // F(t) = E+ + E-, E+ = exp(-x cosh t + v t - M), E- = E+ r with
     // r = e^{-2 v t} carried by a product with e^{-2 v di/64}, recomputed
@@ -748,15 +755,19 @@ __device__ __forceinline__ int i_cost_bucket(T x) {
 template <int B>
 __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     static_assert(B == 6, "thresholds are set for six buckets");
-    double w;
+    // binary32 hardware approximations: only an ordering key (x >= 1e-10 on
+    // this branch keeps v/x and 45/x in binary32 range; smaller x only ever
+    // lands in the last bucket)
+    const float vf = float(v), xf = fmaxf(float(x), 1e-30f);
+    float w;
     if (v * v > x) {
-        const double q = v / x;
-        w = fmin(fm::log64(q + sqrt(fma(q, q, 1.0))), 45.0 / v) + 4.0;   // asinh(v/x)
+        const float q = vf * fm::rcp_hw(xf);
+        w = fminf(fm::log_hw(q + fm::sqrt_hw(fmaf(q, q, 1.0f))), 45.0f * fm::rcp_hw(vf)) + 4.0f;
     } else {
-        const double a = 45.0 / x;
-        w = fm::log64(1.0 + a + sqrt(a * (2.0 + a)));                    // acosh(1 + 45/x)
+        const float a = 45.0f * fm::rcp_hw(xf);
+        w = fm::log_hw(1.0f + a + fm::sqrt_hw(a * (2.0f + a)));   // acosh(1 + 45/x)
     }
-    const double est = w * fma(0.05, v, 1.0) * (1.0 / 0.22);
+    const float est = w * fmaf(0.05f, vf, 1.0f) * (1.0f / 0.22f);
     return (est < 19.0) ? 0 : (est < 29.0) ? 1 : (est < 37.0) ? 2 : (est < 45.0) ? 3
                                                                  : (est < 55.0) ? 4 : 5;
 }

@@ -124,5 +124,27 @@ __host__ __device__ __forceinline__ double log64(double a) {
     return fma(de, kLn2Hi, -((hfsq - fma(s, hfsq + r, de * kLn2Lo)) - f));
 }
 
+// binary32 hardware approximations (v_exp_f32, v_log_f32, v_rcp_f32,
+// v_rsq_f32, v_sqrt_f32; about one binary32 ulp) for quantities that only
+// steer an algorithm (a Newton start and iterate, a step size, a shift,
+// a cost estimate) and never enter a result's arithmetic.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ float exp_hw(float a) {
+    return __builtin_amdgcn_exp2f(a * 1.44269504f);
+}
+__device__ __forceinline__ float log_hw(float a) {
+    return __builtin_amdgcn_logf(a) * 0.693147181f;
+}
+__device__ __forceinline__ float rcp_hw(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ float rsqrt_hw(float a) { return __builtin_amdgcn_rsqf(a); }
+__device__ __forceinline__ float sqrt_hw(float a) { return __builtin_sqrtf(a); }
+#else
+__host__ __device__ inline float exp_hw(float a) { return expf(a); }
+__host__ __device__ inline float log_hw(float a) { return logf(a); }
+__host__ __device__ inline float rcp_hw(float a) { return 1.0f / a; }
+__host__ __device__ inline float rsqrt_hw(float a) { return 1.0f / sqrtf(a); }
+__host__ __device__ inline float sqrt_hw(float a) { return sqrtf(a); }
+#endif
+
 }  // namespace fm
 }  // namespace lbessel
