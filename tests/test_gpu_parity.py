@@ -165,6 +165,23 @@ def test_huge_arguments_match_leading_terms(lb):
     np.testing.assert_allclose(yi, ref, rtol=1e-13)
 
 
+def test_both_sides_of_the_reciprocal_range_switch(lb, oracle):
+    """The Hankel and Debye branches use reciprocals and one merged logarithm
+    below 1e300 and divisions with separate logarithms from 1e300 up; both
+    forms must hold on either side: log I (Debye) across v = 1e300 against
+    the oracle, and both kinds (Hankel) across x = 1e300 against the leading
+    terms, which are exact to rounding there."""
+    v = np.repeat([9.99e299, 1e300, 1.0001e300, 1e305], 4)
+    x = np.tile([1e-3, 1.0, 1e6, 1e12], 4)
+    check64(lb, oracle, "I", v, x, "Debye across v = 1e300")
+    x = np.array([9.9e299, 9.999e299, 1e300, 1.0001e300, 3e300])
+    v = np.array([0.0, 0.5, 2.0, 30.0, 1e3])
+    yi = run(lb, "I", v, x)
+    yk = run(lb, "K", v, x)
+    np.testing.assert_allclose(yi, x - 0.5 * (np.log(2 * np.pi) + np.log(x)), rtol=4e-16)
+    np.testing.assert_allclose(yk, 0.5 * (np.log(np.pi / 2) - np.log(x)) - x, rtol=4e-16)
+
+
 # ---------------------------------------------------------------------------
 # branch-level pins
 # ---------------------------------------------------------------------------
