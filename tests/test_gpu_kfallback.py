@@ -92,6 +92,20 @@ def test_orders_near_zero(lb, oracle):
     assert e.max() <= TOL64, e.max()
 
 
+def test_fallback_region_grid(lb, oracle):
+    """A log-spaced grid over the whole fallback region, x from just above the
+    small-argument switch to the Hankel bound and v up to the Debye bound:
+    peaks from t* = 0 to t* ~ 25, where the step and the peak are found in
+    binary32, against the oracle."""
+    vs = np.concatenate([[0.0], 10 ** np.linspace(-6, np.log10(14.4), 47)])
+    xs = 10 ** np.linspace(np.log10(1.0001e-10), np.log10(17.4), 48)
+    v, x = np.meshgrid(vs, xs)
+    e = _check(lb, oracle, v.ravel(), x.ravel())
+    assert e.max() <= TOL64, e.max()
+    n = lb.k_nodes(torch.from_numpy(v.ravel()).cuda(), torch.from_numpy(x.ravel()).cuda())
+    assert int(n.min().item()) > 0 and int(n.max().item()) < 400
+
+
 def test_node_counts_on_the_stress_grid(lb):
     from paper_2409_08729_amd import workloads as wl
     v, x = wl.m3(1 << 20)
