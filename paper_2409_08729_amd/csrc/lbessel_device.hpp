@@ -607,6 +607,8 @@ __device__ __forceinline__ double br_k_tiny_x(double v, double x) {
 struct KTab {
     double2 eint[64];    // (e^n, e^-n)
     double2 efrac[64];   // (e^{f/64}, e^{-f/64})
+    float2 eint32[64];   // the same, rounded to binary32 (binary32 rule)
+    float2 efrac32[64];
 };
 
 // Cooperative copy of the tables into LDS; every thread of the workgroup
@@ -614,10 +616,13 @@ struct KTab {
 __device__ __forceinline__ void ktab_load(KTab *t) {
     for (int i = threadIdx.x; i < 128; i += blockDim.x) {
         const int j = i & 63;
-        if (i < 64)
+        if (i < 64) {
             t->eint[j] = double2{tables::kExpInt64[j], tables::kExpNegInt64[j]};
-        else
+            t->eint32[j] = float2{float(tables::kExpInt64[j]), float(tables::kExpNegInt64[j])};
+        } else {
             t->efrac[j] = double2{tables::kExpFrac64[j], tables::kExpNegFrac64[j]};
+            t->efrac32[j] = float2{float(tables::kExpFrac64[j]), float(tables::kExpNegFrac64[j])};
+        }
     }
     __syncthreads();
 }
@@ -627,27 +632,23 @@ template <int KIND> struct FbTabSel { using type = KTab; };
 template <> struct FbTabSel<KIND_I> { using type = LgTab; };
 template <int KIND> using FbTab = typename FbTabSel<KIND>::type;
 
-// nodes (may be null): receives the number of integrand evaluations.
-__device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
-                                            int *nodes = nullptr) {
-    constexpr double kGrid = 1.0 / 64.0;
-    constexpr double kDrop = 40.0;          // e^-40 ~ 4e-18 of the peak term
-    constexpr int kMaxNodes = 1024;         // every walk ends (window <= ~40 / h)
-    // peak: root t* > 0 of psi(t) = x sinh t - v tanh(v t) (convex on t >= 0,
-    // psi(0) = 0, psi'(0) = x - v^2 < 0).  tanh(vt) <= 1 and tanh(vt) <= vt
-    // give t* <= asinh(v/x) and t* <= t_s, sinh(t_s)/t_s = v^2/x; two steps of
-    // t <- asinh(R t) from asinh(R), R = v^2/x, approach t_s from below.
-    // Newton starts at the smaller of asinh(v/x) and that estimate: from the
-    // right of t* it decreases monotonically, from the left (where psi' > 0)
-    // its first step lands right of t*; where psi' <= 0 it restarts from the
-    // bound asinh(v/x).  t0 is rounded to the 1/64 grid, so |dt| < 4e-3 ends it.
-    // The peak and the step only place the grid, so they are computed in
-    // binary32 with hardware approximations; the shift, every term, both sums
-    // and the result are binary64 (x >= 1e-10 and v <= ~15 here, so every
-    // binary32 quantity below is in range).
-    const float vf = float(v), xf = float(x);
+// Peak and step of the trapezoid rule on the cosh integral (both rules below).
+// peak: root t* > 0 of psi(t) = x sinh t - v tanh(v t) (convex on t >= 0,
+// psi(0) = 0, psi'(0) = x - v^2 < 0).  tanh(vt) <= 1 and tanh(vt) <= vt
+// give t* <= asinh(v/x) and t* <= t_s, sinh(t_s)/t_s = v^2/x; two steps of
+// t <- asinh(R t) from asinh(R), R = v^2/x, approach t_s from below.
+// Newton starts at the smaller of asinh(v/x) and that estimate: from the
+// right of t* it decreases monotonically, from the left (where psi' > 0)
+// its first step lands right of t*; where psi' <= 0 it restarts from the
+// bound asinh(v/x).  t0 is rounded to the 1/64 grid, so |dt| < 4e-3 ends it.
+// step: h = min(cv / (1 + v/20), cs / sqrt(x cosh t*)), rounded down to a
+// multiple of 1/64 (hq/64, at least 1/64).  The peak and the step only place
+// the grid, so they are computed in binary32 with hardware approximations
+// (x >= 1e-10 and v <= ~15 here, so every quantity is in range).
+__device__ __forceinline__ void k_peak_step(float vf, float xf, bool interior, float cv, float cs,
+                                            int &t0q, int &hq) {
     float t = 0.0f;
-    if (v * v > x) {
+    if (interior) {
         const float q = vf * fm::rcp_hw(xf);
         const float R = vf * q;
         auto asinh_pos = [](float a) { return fm::log_hw(a + fm::sqrt_hw(fmaf(a, a, 1.0f))); };
@@ -674,9 +675,20 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     }
     const float et = fm::exp_hw(t);
     const float ch = 0.5f * (et + fm::rcp_hw(et));
-    const float hf = fminf(0.22f * fm::rcp_hw(fmaf(0.05f, vf, 1.0f)), 0.5f * fm::rsqrt_hw(xf * ch));
-    const int hq = max(int(floorf(hf * 64.0f)), 1);
-    const int t0q = int(rintf(t * 64.0f));
+    const float hf = fminf(cv * fm::rcp_hw(fmaf(0.05f, vf, 1.0f)), cs * fm::rsqrt_hw(xf * ch));
+    hq = max(int(floorf(hf * 64.0f)), 1);
+    t0q = int(rintf(t * 64.0f));
+}
+
+// nodes (may be null): receives the number of integrand evaluations.
+__device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
+                                            int *nodes = nullptr) {
+    constexpr double kGrid = 1.0 / 64.0;
+    constexpr double kDrop = 40.0;          // e^-40 ~ 4e-18 of the peak term
+    constexpr int kMaxNodes = 1024;         // every walk ends (window <= ~40 / h)
+    // the shift, every term, both sums and the result are binary64
+    int t0q, hq;
+    k_peak_step(float(v), float(x), v * v > x, 0.22f, 0.5f, t0q, hq);
     const double h = hq * kGrid;
     // shift M = log-integrand at t0 = t0q/64 in binary64 (log cosh(vt) =
     // vt + log1p(e^{-2vt}) - ln 2), e^{+-t0} from the node tables
@@ -728,6 +740,63 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     if (nodes != nullptr)
         *nodes = cnt;
     return M + fm::log64(0.5 * h * S);
+}
+
+// The same rule in binary32 for the binary32 path (2e-6 target): the window
+// ends 18 below the peak (e^-18 ~ 1.5e-8 of the peak term) and the step
+// doubles to min(0.44 / (1 + v/20), 1 / sqrt(x cosh t*)), which keeps the
+// rule's own error below the binary32 rounding floor (largest error 2.3e-7
+// against the oracle on 3,681 points of the binary32 fallback region, in a
+// binary32 model of this code; ~25 nodes instead of ~50 for the binary64
+// rule there).  Terms, sums and the shift are binary32; e^{+-t} comes from
+// the binary32 copies of the node tables, each term's exponential from the
+// hardware exp2 (its relative error grows with |exponent|, but so does the
+// term's smallness) and the r resets from the library expf.
+__device__ __forceinline__ float br_k_cosh32(float v, float x, const KTab *kt,
+                                             int *nodes = nullptr) {
+    constexpr float kGrid = 1.0f / 64.0f;
+    constexpr float kDrop = 18.0f;
+    constexpr int kMaxNodes = 1024;
+    int t0q, hq;
+    k_peak_step(v, x, v * v > x, 0.44f, 1.0f, t0q, hq);
+    const float h = float(hq) * kGrid;
+    const float2 pi0 = kt->eint32[min(t0q >> 6, 63)];
+    const float2 pf0 = kt->efrac32[t0q & 63];
+    const float vt0 = v * (float(t0q) * kGrid);
+    const float M = fmaf(-0.5f * x, pi0.x * pf0.x + pi0.y * pf0.y, vt0) +
+                    logf(1.0f + expf(-2.0f * vt0)) - Cst<float>::ln2;
+    auto walk = [&](int i0, int di, int j0, float w0, bool past_t0, int &cnt) -> float {
+        const float q2 = expf(-2.0f * v * (float(di) * kGrid));
+        float S = 0.0f, r = 1.0f;
+        for (int j = j0; j < j0 + kMaxNodes; ++j) {
+            const int iq = i0 + j * di;
+            const float tj = float(iq) * kGrid;
+            if (((j - j0) & 15) == 0)
+                r = expf(-2.0f * v * tj);
+            const int aq = abs(iq);
+            const float2 pi = kt->eint32[min(aq >> 6, 63)];
+            const float2 pf = kt->efrac32[aq & 63];
+            const float a = fmaf(-0.5f * x, pi.x * pf.x + pi.y * pf.y, -M);
+            const float ap = fmaf(v, tj, a);
+            const float ep = fm::exp_hw(ap);
+            const float f = fmaf(ep, r, ep);
+            S = (j == j0) ? fmaf(w0, f, S) : S + f;
+            r *= q2;
+            ++cnt;
+            if (ap < -kDrop && (!past_t0 || iq > t0q))
+                break;
+        }
+        return S;
+    };
+    float S;
+    int cnt = 0;
+    if (-x - M >= -kDrop)
+        S = walk(0, hq, 0, 0.5f, true, cnt);
+    else
+        S = walk(t0q, hq, 0, 1.0f, false, cnt) + walk(t0q, -hq, 1, 1.0f, false, cnt);
+    if (nodes != nullptr)
+        *nodes = cnt;
+    return M + logf(0.5f * h * S);
 }
 
 // Debye term-count tier of an order on the Debye branch: 0 = U_13, 1 = U_9,
@@ -884,8 +953,12 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND> *kt)
         return br_series_i<T>(v, x, kt);
     } else {
     constexpr bool u_integral = (VAR == VAR_U_INTEGRAL || VAR == VAR_SIMPSON || VAR == VAR_PAPER);
-    if (!u_integral && x >= T(1e-10))
-        return T(br_k_cosh(double(v), double(x), kt));
+    if (!u_integral && x >= T(1e-10)) {
+        if constexpr (std::is_same<T, float>::value)
+            return br_k_cosh32(v, x, kt);
+        else
+            return br_k_cosh(v, x, kt);
+    }
     if (x < T(1e-10) && v < T(0.3))
         return T(br_k_tiny_x(double(v), double(x)));
     if (VAR == VAR_SIMPSON || VAR == VAR_PAPER)

@@ -583,8 +583,12 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
     T y;
     int c = 0;
     if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB) {
-        if (xx >= T(1e-10))
-            br_k_cosh(double(vv), double(xx), kt, &c);
+        if (xx >= T(1e-10)) {
+            if constexpr (std::is_same<T, float>::value)
+                br_k_cosh32(vv, xx, kt, &c);
+            else
+                br_k_cosh(vv, xx, kt, &c);
+        }
         else if (vv >= T(0.3))
             c = tables::kQuadN;
     }
