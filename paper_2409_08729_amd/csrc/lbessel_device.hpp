@@ -387,14 +387,18 @@ __device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
 // (lgtab_load) before any use.
 struct LgTab {
     double c[tables::kLgIntervals][tables::kLgCoefs];
+    float c32[tables::kLgIntervals][tables::kLgCoefs];   // rounded to binary32
 };
 
 // Cooperative copy of the table into LDS; every thread of the workgroup must
 // call it, before any evaluation of the I series.
 __device__ __forceinline__ void lgtab_load(LgTab *t) {
     constexpr int n = tables::kLgIntervals * tables::kLgCoefs;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        (&t->c[0][0])[i] = (&tables::kLgamma1p64[0][0])[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double c = (&tables::kLgamma1p64[0][0])[i];
+        (&t->c[0][0])[i] = c;
+        (&t->c32[0][0])[i] = float(c);
+    }
     __syncthreads();
 }
 
@@ -406,6 +410,17 @@ __device__ __forceinline__ double lgamma1p_tab(double v, const LgTab *t) {
 #pragma unroll
     for (int i = tables::kLgCoefs - 2; i >= 0; --i)
         s = fma(s, u, c[i]);
+    return s;
+}
+
+__device__ __forceinline__ float lgamma1p_tab(float v, const LgTab *t) {
+    const int j = min(int(2.0f * v), tables::kLgIntervals - 1);
+    const float u = fmaf(4.0f, v, -float(2 * j + 1));
+    const float *c = t->c32[j];
+    float s = c[tables::kLgCoefs - 1];
+#pragma unroll
+    for (int i = tables::kLgCoefs - 2; i >= 0; --i)
+        s = fmaf(s, u, c[i]);
     return s;
 }
 
@@ -424,14 +439,10 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
             break;
     }
     T lg;
-    if constexpr (std::is_same<T, double>::value) {
-        if (v <= 15.0)
-            lg = lgamma1p_tab(v, lt);
-        else
-            lg = lgamma(v + 1.0);
-    } else {
+    if (v <= T(15))
+        lg = lgamma1p_tab(v, lt);
+    else
         lg = lgamma(v + T(1));
-    }
     // log(x/2) as log x - log 2: x/2 can underflow for subnormal x
     return v * (llog(x) - Cst<T>::ln2) - lg + llog(sum);
 }

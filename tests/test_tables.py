@@ -232,3 +232,16 @@ def test_lgamma1p_table():
     # good to ~1e-15 near its minimum, hence the looser second bound
     assert worst < 4e-16, worst
     assert worst_libm < 2e-15, worst_libm
+    # the binary32 copy, evaluated in binary32 as the binary32 path does
+    f32 = np.float32
+    rows32 = [[f32(c) for c in r] for r in rows]
+    worst32 = 0.0
+    for v in np.linspace(0.0, 15.0, 1201, dtype=np.float32):
+        j = min(int(f32(2.0) * v), nint - 1)
+        u = f32(f32(4.0) * v - f32(2 * j + 1))
+        acc = rows32[j][-1]
+        for c in reversed(rows32[j][:-1]):
+            acc = f32(acc * u + c)
+        ref = math.lgamma(1.0 + float(v))
+        worst32 = max(worst32, abs(float(acc) - ref) / max(1.0, abs(ref)))
+    assert worst32 < 1e-6, worst32
