@@ -56,9 +56,11 @@ __device__ __forceinline__ float lexp(float a) { return expf(a); }
 __device__ __forceinline__ float llog(float a) { return logf(a); }
 // exp of an argument known to satisfy |a| < 1e9
 __device__ __forceinline__ double lexp_b(double a) { return fm::exp64_bounded(a); }
-// reciprocal: Newton-refined hardware estimate in binary64 (<= 1 ulp)
+// reciprocal: Newton-refined hardware estimate in binary64 (<= 1 ulp); the
+// hardware v_rcp_f32 (1 ulp) in binary32, for normal arguments (the binary32
+// branches take it of x >= 7, v > 0.1, r >= 1 and series denominators >= 1)
 __device__ __forceinline__ double lrcp(double a) { return fm::rcp_nr(a); }
-__device__ __forceinline__ float lrcp(float a) { return 1.0f / a; }
+__device__ __forceinline__ float lrcp(float a) { return fm::rcp_hw(a); }
 __device__ __forceinline__ float lexp_b(float a) { return expf(a); }
 
 // ---------------------------------------------------------------------------
