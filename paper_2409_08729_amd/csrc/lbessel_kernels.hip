@@ -211,7 +211,7 @@ template <typename T, int NV, int NC, bool STAGE> struct Smem {
     int cnt[NC][TileCfg<NV>::slots][kWaves];             // counts, then offsets
     int start[NC];                                       // first list position per class
     int n_fb, n_fb_u, n_all;                             // list segment ends
-    int uniform;                                         // the only class present, or -1
+    uint32_t wmask[kWaves];                              // classes present, per wave
     int chunk;                                           // next chunk to evaluate
     T res[(NV == 2) ? TileCfg<NV>::tile * 2 : 1];        // log-values of both orders
 };
@@ -320,7 +320,39 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                 sm.cnt[br][s][wave] = __popcll(m);
         }
     }
+    if (lane == 0)
+        sm.wmask[wave] = present;
     __syncthreads();
+
+    // Uniform tile (one class only, e.g. one order whose arguments all fall
+    // in one regime): every wave already runs one branch, so each thread
+    // evaluates its own elements in input order, with coalesced loads and
+    // stores, and the tile skips the scan and the list.  The value of an
+    // element is the same either way.
+    uint32_t tile_mask = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+        tile_mask |= sm.wmask[w];
+    if (NV == 1 && (tile_mask & (tile_mask - 1)) == 0) {   // workgroup-uniform
+        if (tile_mask == 0)
+            return;   // every element was special or out of range (already stored)
+        const int cls = __builtin_ctz(tile_mask);
+        if (cls >= C::f0)
+            fb_tab_load<KIND>(kt);
+        const int b = (cls >= C::f0) ? BR_FB : (cls >= C::u0 ? BR_U : BR_MU);
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            if (done & (1u << r))
+                continue;
+            const int e = r * kThreads + tid;
+            const T v = STAGE ? sm.sv[e] : order_of<T, KIND, OP>(a, base + e);
+            const T x = STAGE ? sm.sx[e] : a.x[base + e];
+            const T y = eval_branch<T, KIND, VAR>(b, v, x, kt);
+            a.out[base + e] = combine<T, KIND, OP>(v, x, T(1), a.p, y, y);
+        }
+        return;
+    }
+
     if (tid < NC) {
         const int br = tid;
         int run = 0;
@@ -334,13 +366,6 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     }
     __syncthreads();
     if (tid == 0) {
-        int only = -1, nclass = 0;
-        for (int b = 0; b < NC; ++b)
-            if (sm.start[b] > 0) {
-                only = b;
-                ++nclass;
-            }
-        sm.uniform = (nclass == 1) ? only : -1;
         // list order: fallback buckets from costliest down, Debye tiers from
         // costliest (U_13) down, Hankel
         int pos = 0;
@@ -367,25 +392,6 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     const int n_all = sm.n_all;
     if (n_fb > 0)                                 // workgroup-uniform
         fb_tab_load<KIND>(kt);
-
-    // Uniform tile (one class only, e.g. one order whose arguments all fall
-    // in one regime): every wave already runs one branch, so each thread
-    // evaluates its own elements in input order, with coalesced loads and
-    // stores and no list.  The value of an element is the same either way.
-    if (NV == 1 && sm.uniform >= 0) {
-        const int b = (sm.uniform >= C::f0) ? BR_FB : (sm.uniform >= C::u0 ? BR_U : BR_MU);
-#pragma unroll
-        for (int r = 0; r < EPT; ++r) {
-            if (done & (1u << r))
-                continue;
-            const int e = r * kThreads + tid;
-            const T v = STAGE ? sm.sv[e] : order_of<T, KIND, OP>(a, base + e);
-            const T x = STAGE ? sm.sx[e] : a.x[base + e];
-            const T y = eval_branch<T, KIND, VAR>(b, v, x, kt);
-            a.out[base + e] = combine<T, KIND, OP>(v, x, T(1), a.p, y, y);
-        }
-        return;
-    }
 
     // 3. scatter evaluation ids in list order
 #pragma unroll
