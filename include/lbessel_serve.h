@@ -20,8 +20,9 @@
  *      the request needs is free (inputs, outputs, workspace).  Admission
  *      is strictly FIFO, so a large request is never starved.
  *   3. continuous batching: whenever one of the server's streams is free,
- *      every admitted request not yet launched (up to the batch caps) forms
- *      the next batch: its host inputs are copied in, all evaluation
+ *      the admitted requests not yet launched form the next batch, in FIFO
+ *      order up to the batch caps (a large evaluation request or a vMF fit
+ *      goes out alone): its host inputs are copied in, all evaluation
  *      requests of one (kind, precision) run as ONE segmented launch
  *      (lbessel_eval_segments), vMF requests run their column-sum and
  *      Newton kernels, and the outputs are copied back.  Requests that
@@ -72,6 +73,9 @@ typedef struct lbessel_server_config {
     int64_t max_batch_elems;    /* evaluation pairs per batch (>= 1); a single
                                    larger request still forms a batch alone    */
     int poll_us;                /* scheduler sleep while batches run; 0 = spin  */
+    int64_t solo_elems;         /* evaluation requests of at least this many
+                                   pairs, and vMF fits, form a batch alone
+                                   (>= 1)                                       */
 } lbessel_server_config_t;
 
 /* Request states in lbessel_request_info_t.state */
@@ -107,10 +111,12 @@ typedef struct lbessel_server_stats {
 } lbessel_server_stats_t;
 
 /* Default configuration: 2 GiB arena, 8 streams, batched, 64 requests and
- * 2^18 pairs per batch, spinning scheduler.  With host-resident requests the
- * server is bound by the copies: small batches keep a request from waiting
- * long for its batch-mates' inputs, while the many small requests still
- * share launches. */
+ * 2^18 pairs per batch, evaluation requests of 2^16 pairs or more and vMF
+ * fits alone, spinning scheduler.  With host-resident requests the server is
+ * bound by the copies: a large request gains nothing from sharing a launch
+ * and would make its batch-mates wait for its inputs, so only the small
+ * requests, for which a launch costs as much as their copies, share
+ * segmented launches. */
 void lbessel_server_default_config(lbessel_server_config_t *cfg);
 
 /*

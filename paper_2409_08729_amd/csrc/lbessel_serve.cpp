@@ -299,11 +299,14 @@ void lbessel_server::run() {
             while (!admitted.empty() && sl.reqs.size() < max_req) {
                 Request *r = admitted.front();
                 const int64_t add = (r->type == REQ_EVAL) ? r->n : 0;
-                if (!sl.reqs.empty() && elems + add > cfg.max_batch_elems)
+                const bool solo = (r->type != REQ_EVAL) || add >= cfg.solo_elems;
+                if (!sl.reqs.empty() && (solo || elems + add > cfg.max_batch_elems))
                     break;
                 elems += add;
                 sl.reqs.push_back(r);
                 admitted.pop_front();
+                if (solo)
+                    break;
             }
             const int64_t b = next_batch++;
             const double t = now();
@@ -390,13 +393,14 @@ void lbessel_server_default_config(lbessel_server_config_t *cfg) {
     cfg->max_batch_requests = 64;
     cfg->max_batch_elems = int64_t(1) << 18;
     cfg->poll_us = 0;
+    cfg->solo_elems = int64_t(1) << 16;
 }
 
 int lbessel_server_create(const lbessel_server_config_t *cfg, lbessel_server_t **out) {
     if (cfg == nullptr || out == nullptr || cfg->arena_bytes <= 0 || cfg->streams < 1 ||
         cfg->streams > 16 || (cfg->mode != LBESSEL_SERVE_BATCHED && cfg->mode != LBESSEL_SERVE_PLAIN) ||
         cfg->max_batch_requests < 1 || cfg->max_batch_requests > 1024 ||
-        cfg->max_batch_elems < 1 || cfg->poll_us < 0)
+        cfg->max_batch_elems < 1 || cfg->poll_us < 0 || cfg->solo_elems < 1)
         return LBESSEL_EINVAL;
     *out = nullptr;
     int dev = 0;

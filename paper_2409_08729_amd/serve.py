@@ -27,7 +27,8 @@ ETIMEOUT = -5
 class Config(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_int64), ("streams", ctypes.c_int),
                 ("mode", ctypes.c_int), ("max_batch_requests", ctypes.c_int),
-                ("max_batch_elems", ctypes.c_int64), ("poll_us", ctypes.c_int)]
+                ("max_batch_elems", ctypes.c_int64), ("poll_us", ctypes.c_int),
+                ("solo_elems", ctypes.c_int64)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -101,14 +102,16 @@ class Server:
 
     def __init__(self, mode: str = "batched", arena_bytes: int | None = None,
                  streams: int | None = None, max_batch_requests: int | None = None,
-                 max_batch_elems: int | None = None, poll_us: int | None = None):
+                 max_batch_elems: int | None = None, poll_us: int | None = None,
+                 solo_elems: int | None = None):
         lib = _lib()
         cfg = Config()
         lib.lbessel_server_default_config(ctypes.byref(cfg))
         cfg.mode = MODES[mode]
         for name, val in (("arena_bytes", arena_bytes), ("streams", streams),
                           ("max_batch_requests", max_batch_requests),
-                          ("max_batch_elems", max_batch_elems), ("poll_us", poll_us)):
+                          ("max_batch_elems", max_batch_elems), ("poll_us", poll_us),
+                          ("solo_elems", solo_elems)):
             if val is not None:
                 setattr(cfg, name, int(val))
         self.config = {name: getattr(cfg, name) for name, _ in Config._fields_}

@@ -107,3 +107,33 @@ def test_server_needs_a_device():
         pytest.skip("a GPU is visible: covered by the GPU serving tests")
     with pytest.raises(Exception, match="no usable device"):
         serve.Server()
+
+
+def test_server_config_layout_and_defaults(lib, tmp_path):
+    """The binding's Config mirrors lbessel_server_config_t (field offsets and
+    size from the C compiler), and the library's defaults are the documented
+    ones."""
+    import shutil
+    import subprocess
+    from paper_2409_08729_amd import serve
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [name for name, _ in serve.Config._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbessel_serve.h"\n'
+                   "int main(void) {\n"
+                   '  printf("%zu", sizeof(lbessel_server_config_t));\n'
+                   + "".join(f'  printf(" %zu", offsetof(lbessel_server_config_t, {f}));\n'
+                             for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(t) for t in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(serve.Config)
+    assert got[1:] == [getattr(serve.Config, f).offset for f in fields]
+    cfg = serve.Config()
+    serve._lib().lbessel_server_default_config(ctypes.byref(cfg))
+    assert (cfg.arena_bytes, cfg.streams, cfg.mode, cfg.max_batch_requests, cfg.max_batch_elems,
+            cfg.poll_us, cfg.solo_elems) == (2 << 30, 8, 0, 64, 1 << 18, 0, 1 << 16)
