@@ -563,10 +563,24 @@ def main():
             "all_K_launches": {"frac": all_ops / all_dur / 1e12 / VALU_PEAK_TOPS,
                                "ms": all_dur * 1e3}}
 
+    ci = om["I_f64"]
+
+    def i_ops(j):
+        c = mix[(j, "I")]
+        return (c["mu20"] * ci["mu20"] + sum(c[u] * ci[u] for u in ("u13", "u9", "u6", "u4"))
+                + c["fallback"] * ci["fallback"])
+
     kern = {}
     for (name, kind), ts in per.items():
-        n = [v.numel() for nm, v, _ in sets if nm == name][0]
-        kern[f"{kind}:{name}"] = {"ms": float(np.mean(ts)), "G_evals_s": n / np.mean(ts) / 1e6}
+        j = [i for i, (nm, _, _) in enumerate(sets) if nm == name][0]
+        n = sets[j][1].numel()
+        ops_j = k_ops(j) if kind == "K" else i_ops(j)
+        kern[f"{kind}:{name}"] = {"ms": float(np.mean(ts)), "G_evals_s": n / np.mean(ts) / 1e6,
+                                  "valu_frac": ops_j / (float(np.mean(ts)) * 1e-3) / 1e12
+                                  / VALU_PEAK_TOPS}
+    roof["per_launch_note"] = ("kernels[...].valu_frac: op-model VALU work / launch time / peak for "
+                               "every launch; the I series is charged its cost at v = 3, x = 5 "
+                               "(exact for launches without series elements, v >= 2^4)")
     i_ms = sum(np.mean(ts) for (nm, kd), ts in per.items() if kd == "I")
     k_ms = sum(np.mean(ts) for (nm, kd), ts in per.items() if kd == "K")
 
