@@ -716,6 +716,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     // every 16 nodes (its relative error stays below 16 ulp, and it only
     // enters through E-).  Stops after the first node with log E+ < -kDrop
     // (and, for a walk from 0, past t0).
+    const double lead = fm::pin_v(fm::kExpLead);
     auto walk = [&](int i0, int di, int j0, double w0, bool past_t0, int &cnt) -> double {
         const double q2 = fm::exp64_bounded(-2.0 * v * (di * kGrid));
         double S = 0.0, r = 1.0;
@@ -731,7 +732,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
             const double2 pf = kt->efrac[aq & 63];
             const double a = fma(-0.5 * x, pi.x * pf.x + pi.y * pf.y, -M);
             const double ap = fma(v, tj, a);
-            const double ep = fm::exp64_bounded(ap);
+            const double ep = fm::exp64_bounded_lc(ap, lead);
             const double f = fma(ep, r, ep);
             S = (j == j0) ? fma(w0, f, S) : S + f;
             r *= q2;

@@ -81,6 +81,37 @@ __host__ __device__ __forceinline__ double exp64_core(double y, double &k_out) {
     return p;
 }
 
+// The leading coefficient of exp64_core's polynomial, held in a VGPR pair by
+// a loop that calls exp64_bounded_lc many times: the first Horner step then
+// reads one SGPR constant instead of copying both into VGPRs every call.
+constexpr double kExpLead = 0x1.af631d0059becp-26;
+__host__ __device__ __forceinline__ double pin_v(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(a));
+#endif
+    return a;
+}
+
+// exp64_bounded with the leading coefficient lead == kExpLead supplied by the
+// caller (same result bits).
+__host__ __device__ __forceinline__ double exp64_bounded_lc(double y, double lead) {
+    const double k = rint(y * kLog2e);
+    double r = fma(-k, kLn2Hi, y);
+    r = fma(-k, kLn2Lo, r);
+    double p = fma_c(lead, r, 0x1.28b4057f44145p-22);
+    p = fma_c(p, r, 0x1.71ddf5749d126p-19);
+    p = fma_c(p, r, 0x1.a01991ac8730ap-16);
+    p = fma_c(p, r, 0x1.a01a01b14378fp-13);
+    p = fma_c(p, r, 0x1.6c16c187fbe02p-10);
+    p = fma_c(p, r, 0x1.111111110f225p-7);
+    p = fma_c(p, r, 0x1.555555554f0cfp-5);
+    p = fma_c(p, r, 0x1.555555555555ap-3);
+    p = fma_c(p, r, 0x1.0000000000011p-1);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, int(k));
+}
+
 // exp(y) for finite y; below about -745 gives 0, above about 709.8 +inf.
 __host__ __device__ __forceinline__ double exp64(double y) {
     double k;
