@@ -1,19 +1,23 @@
 // HIP kernels and C-ABI entry points of liblbessel (gfx950, wave64).
 //
 // Grouped kernel (every public forward / derivative / vMF call):
-//   one workgroup = 256 threads = 4 wavefronts owns a tile of consecutive
-//   elements (2048 for one evaluation per element, 1024 for two).
+//   one workgroup = 256 threads = 4 wavefronts owns a tile of 1024
+//   consecutive elements (4 per thread; two evaluations per element, orders
+//   v and v + 1, for the derivatives and the vMF gradient).
 //   1. coalesced loads of (v, x); special values are resolved at once; every
-//      other evaluation gets its branch from its own (v, x);
-//   2. per branch, wavefront ballots + popcounts give per-wave counts and one
-//      short scan turns them into offsets of a branch-sorted list in LDS
-//      (fallback first, then Debye, then Hankel: most expensive first);
+//      other evaluation gets its class from its own (v, x): branch, Debye
+//      term-count tier, fallback cost bucket;
+//   2. per class present in a wavefront, ballots + popcounts give per-wave
+//      counts.  A tile with a single class evaluates its elements in place
+//      (coalesced, no list); otherwise one short scan turns the counts into
+//      offsets of a class-sorted list in LDS (fallback buckets, costliest
+//      first, then the Debye tiers, then Hankel);
 //   3. the list is cut into 64-entry chunks that the wavefronts take from an
-//      LDS counter: each wavefront runs one branch on a full wave except for
-//      at most two boundary chunks per tile, and expensive chunks spread over
-//      the four wavefronts;
-//   4. results go straight to HBM (one evaluation per element) or to LDS and
-//      are combined per element (two orders per element for derivatives).
+//      LDS counter, so a wavefront runs one class except in the chunks that
+//      straddle two, and expensive chunks spread over the four wavefronts;
+//   4. results go straight to HBM, or (log K, whose pairs are staged in LDS)
+//      into LDS and out in one coalesced store, or into LDS to be combined
+//      per element (two orders per element).
 // The branch of an evaluation depends only on its own (v, x), never on its
 // neighbours, so the grouped and the ungrouped kernel give the same bits.
 #include <hip/hip_runtime.h>
@@ -172,8 +176,9 @@ template <int NV> struct TileCfg {
     static constexpr int slots = ept * NV;               // evaluations per thread
 };
 
-// Classes an evaluation is sorted into inside a tile: 0 = Hankel, 1 = Debye,
-// 2 + b = fallback bucket b.  The fallbacks' costs vary ~10x with (v, x):
+// Classes an evaluation is sorted into inside a tile: Hankel, Debye and the
+// fallback (three classes for the two-order operations).  The fallbacks'
+// costs vary ~10x with (v, x):
 // the K integral's node count and the I series' term count.  For the
 // one-order operations the fallback is therefore split into buckets by an
 // estimate of that count (kKBuckets for K, kIBuckets for I), so the lanes of
