@@ -596,6 +596,25 @@ __device__ __forceinline__ double br_k_tiny_x(double v, double x) {
     return fm::log64(k);
 }
 
+// K_v at tiny x for v >= 0.3 (the rest of the fallback below x = 1e-10): the
+// same two-term form, K_v(x) = [Gamma(1+v) y^{-v} - Gamma(1-v) y^{v}] / (2v),
+// y = x/2 < 5e-11, in log form.  The second term, relative Gamma(1-v) /
+// Gamma(1+v) y^{2v} <= ~1e-6, is kept for v < 0.9; from 0.9 up it is below
+// 1e-17 except within ~1e-4 of the integers, where it and the O(y^2) term
+// of the first series both grow like 1/(v - n) and cancel to O(y^2 log y)
+// (the logarithmic terms of DLMF 10.31.1): both are dropped there.  Every
+// other neglected term is O(y^2) relative.
+__device__ __forceinline__ double br_k_small_x(double v, double x) {
+    const double ly = fm::log64(x) - Cst<double>::ln2;          // log y, no underflow
+    const double g1 = tgamma(1.0 + v);                          // v <= ~15: finite
+    double lk = fm::log64(g1 / (2.0 * v)) - v * ly;
+    if (v < 0.9) {
+        const double r = tgamma(1.0 - v) / g1 * fm::exp64(2.0 * v * ly);
+        lk += fm::log64(1.0 - r);
+    }
+    return lk;
+}
+
 // ---------------------------------------------------------------------------
 // K_v by the trapezoid rule on the cosh integral (fallback for x >= 1e-10)
 // ---------------------------------------------------------------------------
@@ -975,6 +994,8 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND> *kt)
     }
     if (x < T(1e-10) && v < T(0.3))
         return T(br_k_tiny_x(double(v), double(x)));
+    if (!u_integral)   // x < 1e-10, v >= 0.3
+        return T(br_k_small_x(double(v), double(x)));
     if (VAR == VAR_SIMPSON || VAR == VAR_PAPER)
         return br_quad_k<T, double, true>(v, x);
     return br_quad_k<T, double>(v, x);

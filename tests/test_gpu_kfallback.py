@@ -84,6 +84,20 @@ def test_small_argument_switch(lb, oracle, dtype):
     assert e.max() <= (TOL64 if dtype == torch.float64 else TOL32), e.max()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_small_argument_form_above_order_0_3(lb, oracle, dtype):
+    """x < 1e-10, v >= 0.3: the two-term small-argument form, including its
+    switch at v = 0.9 and orders within 1e-7 of the integers, where the
+    dropped terms cancel; x down to 1e-300 (1e-38 in binary32)."""
+    g = np.random.default_rng(31)
+    lo_x = -300 if dtype == torch.float64 else -37
+    v = np.concatenate([g.uniform(0.3, 14.4, 400), [0.3, 0.5, 0.8999, 0.9, 0.9001, 0.99999, 1.0,
+                        1.00001, 1.5, 2.0 - 1e-7, 2.0, 2.0 + 1e-7, 3.0, 7.0, 14.0, 14.4]])
+    x = np.concatenate([10 ** g.uniform(lo_x, -10.0001, 400), 10 ** g.uniform(lo_x, -10.0001, 16)])
+    e = _check(lb, oracle, v, x, dtype)
+    assert e.max() <= (TOL64 if dtype == torch.float64 else TOL32), e.max()
+
+
 def test_orders_near_zero(lb, oracle):
     g = np.random.default_rng(12)
     v = np.concatenate([10 ** g.uniform(-300, -3, 800), np.zeros(100)])
