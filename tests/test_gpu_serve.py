@@ -220,3 +220,22 @@ def test_empty_and_tiny_requests(lb):
         assert srv.wait(t0, 30)["status"] == 0
         assert srv.wait(t1, 30)["status"] == 0
     assert out.item() == lb.log_iv(one_v.cuda(), one_x.cuda()).item()
+
+
+def test_large_requests_and_fits_go_out_alone(lb):
+    """Evaluation requests of at least solo_elems pairs and vMF fits form a
+    batch of their own; smaller evaluation requests still share batches."""
+    from paper_2409_08729_amd import serve
+    reqs = _make_requests(64, seed=21, max_pairs=300_000)
+    _fresh_outputs(reqs)
+    solo = 1 << 15
+    with serve.Server("batched", arena_bytes=1 << 30, solo_elems=solo) as srv:
+        infos = srv.replay(_items(reqs, [0.0] * len(reqs)), timeout=120)
+    assert all(i["status"] == 0 for i in infos)
+    members = {}
+    for r, i in zip(reqs, infos):
+        members.setdefault(i["batch"], []).append(r)
+    for r, i in zip(reqs, infos):
+        if r["type"] == "vmf" or r["n"] >= solo:
+            assert len(members[i["batch"]]) == 1, (r["type"], r.get("n"))
+    assert any(len(m) > 1 for m in members.values())
