@@ -663,6 +663,49 @@ __global__ __launch_bounds__(kThreads) void k_colsum_part(const float *__restric
     part[int64_t(blockIdx.y) * p + j] = s;
 }
 
+// The same with four consecutive columns per thread and 16-byte loads (p a
+// multiple of 4, X 16-byte aligned), four rows in flight per step; every
+// column is still summed over its rows in order.
+__global__ __launch_bounds__(kThreads) void k_colsum_part4(const float *__restrict__ X,
+                                                           const double *__restrict__ inv,
+                                                           int64_t n, int64_t p, int64_t rows_per,
+                                                           double *__restrict__ part) {
+    const int64_t j = (int64_t(blockIdx.x) * kThreads + threadIdx.x) * 4;
+    if (j >= p)
+        return;
+    const int64_t r0 = int64_t(blockIdx.y) * rows_per;
+    const int64_t r1 = (r0 + rows_per < n) ? r0 + rows_per : n;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t i = r0;
+    for (; i + 4 <= r1; i += 4) {
+        float4 a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a[k] = *reinterpret_cast<const float4 *>(X + (i + k) * p + j);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double w = inv[i + k];
+            s0 = fma(double(a[k].x), w, s0);
+            s1 = fma(double(a[k].y), w, s1);
+            s2 = fma(double(a[k].z), w, s2);
+            s3 = fma(double(a[k].w), w, s3);
+        }
+    }
+    for (; i < r1; ++i) {
+        const float4 a = *reinterpret_cast<const float4 *>(X + i * p + j);
+        const double w = inv[i];
+        s0 = fma(double(a.x), w, s0);
+        s1 = fma(double(a.y), w, s1);
+        s2 = fma(double(a.z), w, s2);
+        s3 = fma(double(a.w), w, s3);
+    }
+    double *o = part + int64_t(blockIdx.y) * p + j;
+    o[0] = s0;
+    o[1] = s1;
+    o[2] = s2;
+    o[3] = s3;
+}
+
 // colsum[j] = sum_r part[r, j] in slice order.
 __global__ __launch_bounds__(kThreads) void k_colsum_final(const double *__restrict__ part,
                                                            int64_t nslices, int64_t p,
@@ -983,8 +1026,16 @@ int lbessel_eval_ungrouped(int kind, int precision, const void *v, const void *x
 
 // Row slices of the column-sum pass: enough workgroups to fill the chip
 // (>= 2048) while every slice keeps >= 64 rows.
-static int64_t vmf_slices(int64_t n, int64_t p) {
-    const int64_t col_blocks = (p + kThreads - 1) / kThreads;
+// Columns per thread of the column-sum pass: 4 with 16-byte loads for wide
+// rows (p >= 4096) that start 16-byte aligned, else 1.  Narrower rows keep
+// one column per thread: four would leave too few column blocks, and the
+// extra slices cost more in the final reduction than the wider loads save.
+static int vmf_cols_per_thread(const void *X, int64_t p) {
+    return (p >= 4096 && (p & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) ? 4 : 1;
+}
+
+static int64_t vmf_slices(int64_t n, int64_t p, int cpt) {
+    const int64_t col_blocks = (p + int64_t(kThreads) * cpt - 1) / (int64_t(kThreads) * cpt);
     int64_t r = (2048 + col_blocks - 1) / col_blocks;
     const int64_t max_r = (n + 63) / 64;
     if (r > max_r)
@@ -999,7 +1050,10 @@ static int64_t vmf_slices(int64_t n, int64_t p) {
 int64_t lbessel_vmf_colsum_workspace(int64_t n, int64_t p) {
     if (n < 0 || p < 0)
         return LBESSEL_EINVAL;
-    return (vmf_slices(n, p) * p + n) * int64_t(sizeof(double));
+    // the 4-column pass (when taken) uses the most slices; the 1-column pass
+    // fits inside
+    const int cpt = (p >= 4096 && (p & 3) == 0) ? 4 : 1;
+    return (vmf_slices(n, p, cpt) * p + n) * int64_t(sizeof(double));
 }
 
 int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum, double *sumsq,
@@ -1011,9 +1065,11 @@ int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
     const int64_t need = lbessel_vmf_colsum_workspace(n, p);
     if (colsum == nullptr || work == nullptr || work_bytes < need || (n > 0 && X == nullptr))
         return LBESSEL_EINVAL;
-    const int64_t slices = vmf_slices(n, p);
+    const int cpt = vmf_cols_per_thread(X, p);
+    const int64_t slices = vmf_slices(n, p, cpt);
     const int64_t rows_per = (n + slices - 1) / slices;
     const int64_t col_blocks = (p + kThreads - 1) / kThreads;
+    const int64_t col_blocks_cpt = (p + int64_t(kThreads) * cpt - 1) / (int64_t(kThreads) * cpt);
     if (col_blocks > int64_t(0x7fffffff))
         return LBESSEL_EINVAL;
     double *part = static_cast<double *>(work);
@@ -1021,8 +1077,12 @@ int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
     hipStream_t st = static_cast<hipStream_t>(s);
     if (n > 0)
         hipLaunchKernelGGL(k_rownorm_inv, dim3(uint32_t(n)), dim3(kThreads), 0, st, X, p, inv);
-    hipLaunchKernelGGL(k_colsum_part, dim3(uint32_t(col_blocks), uint32_t(slices)),
-                       dim3(kThreads), 0, st, X, inv, n, p, rows_per, part);
+    if (cpt == 4)
+        hipLaunchKernelGGL(k_colsum_part4, dim3(uint32_t(col_blocks_cpt), uint32_t(slices)),
+                           dim3(kThreads), 0, st, X, inv, n, p, rows_per, part);
+    else
+        hipLaunchKernelGGL(k_colsum_part, dim3(uint32_t(col_blocks), uint32_t(slices)),
+                           dim3(kThreads), 0, st, X, inv, n, p, rows_per, part);
     hipLaunchKernelGGL(k_colsum_final, dim3(uint32_t(col_blocks)), dim3(kThreads), 0, st, part,
                        slices, p, colsum);
     if (sumsq != nullptr)
