@@ -631,9 +631,21 @@ __global__ __launch_bounds__(kThreads) void k_rownorm_inv(const float *__restric
     const int64_t row = blockIdx.x;
     const float *r = X + row * p;
     double ss = 0.0;
-    for (int64_t j = threadIdx.x; j < p; j += kThreads) {
-        const double a = r[j];
-        ss = fma(a, a, ss);
+    if ((p & 3) == 0 && (reinterpret_cast<uintptr_t>(r) & 15) == 0) {
+        // 16-byte loads (same per-thread order: element 4j, 4j+1, ... of each load)
+        const float4 *r4 = reinterpret_cast<const float4 *>(r);
+        for (int64_t j = threadIdx.x; j < (p >> 2); j += kThreads) {
+            const float4 a = r4[j];
+            ss = fma(double(a.x), double(a.x), ss);
+            ss = fma(double(a.y), double(a.y), ss);
+            ss = fma(double(a.z), double(a.z), ss);
+            ss = fma(double(a.w), double(a.w), ss);
+        }
+    } else {
+        for (int64_t j = threadIdx.x; j < p; j += kThreads) {
+            const double a = r[j];
+            ss = fma(a, a, ss);
+        }
     }
     for (int off = 32; off > 0; off >>= 1)
         ss += __shfl_down(ss, off);
