@@ -430,14 +430,23 @@ template <typename T>
 __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     const T hx = T(0.5) * x;
     const T q = hx * hx;
+    // two terms per step with one reciprocal: a_k/a_{k-1} = q / d_k,
+    // d_k = k (k + v), so a_k = a_{k-1} q d_{k+1} / (d_k d_{k+1}) and
+    // a_{k+1} = a_{k-1} q^2 / (d_k d_{k+1}).  The stop test runs on the second
+    // term of a pair, so at most one term more than a per-term test is summed.
+    const T q2 = q * q;
     T term = T(1);
     T sum = T(1);
-    for (int k = 1; k < 200; ++k) {
-        const T fk = T(k);
-        const T den = fk * (fk + v);
-        term = term * q * lrcp(den);
+    for (int k = 1; k < 200; k += 2) {
+        const T f0 = T(k), f1 = T(k + 1);
+        const T d0 = f0 * (f0 + v);
+        const T d1 = f1 * (f1 + v);
+        const T r = lrcp(d0 * d1);
+        const T t0 = term * q * d1 * r;
+        term = term * q2 * r;
+        sum = sum + t0;
         sum = sum + term;
-        if (den > T(2) * q && term < Cst<T>::series_eps * sum)
+        if (d1 > T(2) * q && term < Cst<T>::series_eps * sum)
             break;
     }
     T lg;
