@@ -860,12 +860,15 @@ __device__ __forceinline__ int i_cost_bucket(T x) {
     return (x < T(0.1)) ? 0 : (x < T(1)) ? 1 : (x < T(5)) ? 2 : 3;
 }
 
-// Cost bucket 0..B-1 of a K fallback element: a rough count of the nodes
-// br_k_cosh will visit (window width / step), cut at fixed thresholds.  Only
-// used to order work inside a tile; any value is correct.
+// Cost bucket of a K fallback element: 0..5, a rough count of the nodes
+// br_k_cosh will visit (window width / step) cut at fixed thresholds, or 6
+// for an interior window (the peak estimate stands more than 40 above the
+// integrand at t = 0), whose right and left walks would otherwise run one
+// after the other in chunks shared with the single walk of windows that
+// start at 0.  Only used to order work inside a tile; any value is correct.
 template <int B>
 __device__ __forceinline__ int k_cost_bucket(double v, double x) {
-    static_assert(B == 6, "thresholds are set for six buckets");
+    static_assert(B == 7, "six cost buckets and the interior-window class");
     // binary32 hardware approximations: only an ordering key (x >= 1e-10 on
     // this branch keeps v/x and 45/x in binary32 range; smaller x only ever
     // lands in the last bucket)
@@ -873,7 +876,20 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     float w;
     if (v * v > x) {
         const float q = vf * fm::rcp_hw(xf);
-        w = fminf(fm::log_hw(q + fm::sqrt_hw(fmaf(q, q, 1.0f))), 45.0f * fm::rcp_hw(vf)) + 4.0f;
+        const float tu = fm::log_hw(q + fm::sqrt_hw(fmaf(q, q, 1.0f)));
+        w = fminf(tu, 45.0f * fm::rcp_hw(vf)) + 4.0f;
+        // interior window (both walks): the log-integrand at a peak estimate
+        // stands more than 40 above its value -x at t = 0
+        const float R = vf * q;
+        auto asinh_pos = [](float a) { return fm::log_hw(a + fm::sqrt_hw(fmaf(a, a, 1.0f))); };
+        float ts = asinh_pos(R);
+        ts = asinh_pos(R * ts);
+        ts = asinh_pos(R * ts);
+        const float t = fminf(tu, ts);
+        const float et = fm::exp_hw(t);
+        const float phi = fmaf(-0.5f * xf, et + fm::rcp_hw(et), vf * t) + xf;
+        if (phi > 40.7f)
+            return 6;
     } else {
         const float a = 45.0f * fm::rcp_hw(xf);
         w = fm::log_hw(1.0f + a + fm::sqrt_hw(a * (2.0f + a)));   // acosh(1 + 45/x)

@@ -181,13 +181,14 @@ template <int NV> struct TileCfg {
 // costs vary ~10x with (v, x):
 // the K integral's node count and the I series' term count.  For the
 // one-order operations the fallback is therefore split into buckets by an
-// estimate of that count (kKBuckets for K, kIBuckets for I), so the lanes of
-// one 64-entry chunk run loops of similar length.  List order: costliest
+// estimate of that count (kKBuckets for K: six by node count and one for the
+// interior windows; kIBuckets for I), so the lanes of one 64-entry chunk run
+// loops of similar length.  List order: costliest
 // bucket first, then the cheaper ones, Debye, Hankel.
 // The Debye class is split the same way into its term-count tiers (U_13,
 // U_9, U_6, U_4; u_tier), which differ ~2x in cost.
 // Class ids: 0 = Hankel, 1..ub = Debye tier, 1+ub.. = fallback bucket.
-constexpr int kKBuckets = 6;
+constexpr int kKBuckets = 7;
 constexpr int kIBuckets = 4;
 template <int KIND, int OP, int VAR> struct Classes {
     static constexpr bool one = (OpTraits<OP>::nv == 1);
