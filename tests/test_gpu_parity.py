@@ -279,6 +279,29 @@ def test_grouped_equals_ungrouped_bitwise(lb, kind, dtype):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (name, n)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_large_launches_equal_ungrouped_bitwise(lb, kind, dtype):
+    """Launches of 2^24 elements and more, including tiles with a single
+    fallback element and a ragged last tile: every value equals the
+    one-element-per-thread kernel's."""
+    f = lb.log_iv if kind == "I" else lb.log_kv
+    vs, xs = wl.m3(n=(1 << 25) + 777, seed=13)
+    cases = {"stress_2^25+777": (vs, xs), "stress_2^24": (vs[:1 << 24], xs[:1 << 24])}
+    n = (1 << 24) + 5
+    v = np.full(n, 1.0)
+    x = np.full(n, 50.0)                 # Hankel
+    v[::1024], x[::1024] = 3.0, 5.0      # one fallback element per tile
+    v[5::4096], x[5::4096] = 0.5, 1e-4   # a costlier bucket every 4th tile
+    v[-3:], x[-3:] = 3.0, 5.0            # fallback in the ragged last tile
+    cases["sparse_fallback"] = (v, x)
+    for name, (v, x) in cases.items():
+        dv, dx = dev(v, dtype), dev(x, dtype)
+        a = host(f(dv, dx))
+        b = host(lb.eval_ungrouped(kind, dv, dx))
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), name
+
+
 def test_empty_input(lb):
     e = torch.empty(0, dtype=torch.float64, device="cuda:0")
     assert lb.log_iv(e, e).numel() == 0
