@@ -639,39 +639,48 @@ __device__ __forceinline__ double br_k_small_x(double v, double x) {
 // are multiples of 1/64, so every t_j is exact and the only rounding in a
 // term is that of its own exponent.  The sum is kept relative to the
 // log-integrand at the grid point nearest t* (log-sum shift).
-// e^t and e^-t at the grid nodes of br_k_cosh (t = i/64, 0 <= i < 4096) as
-// e^{+-(i>>6)} e^{+-(i&63)/64}, indices clamped to the tables (a node beyond
-// t = 64 only ever ends a walk); two correctly rounded table entries and one
-// product each (<= 1.5 ulp), so a node needs no division.  Each entry holds
-// the pair (e^+, e^-), read with one 16-byte LDS load.  The tables are copied
-// into LDS by the kernel (ktab_load) before any use.
+// e^t and e^-t at the grid nodes of br_k_cosh (t = i/64, 0 <= i < 2048) as
+// e^{+-(i>>6)} e^{+-(i&63)/64}, integer part clamped to the table; two
+// correctly rounded table entries and one product each (<= 1.5 ulp), so a
+// node needs no division.  Each entry holds the pair (e^+, e^-), read with
+// one 16-byte LDS load.  No walk reaches t = 32: on the fallback region
+// (x >= 1e-10, v <= 14.5) the log-integrand has dropped 40 below its peak by
+// t ~ 29 (the peak is below t = 27), and each walk ends there.  The tables
+// are copied into LDS by the kernel (ktab_load) before any use; the binary32
+// rule reads the same entries rounded to binary32.
+constexpr int kKTabInt = 32;
 struct KTab {
-    double2 eint[64];    // (e^n, e^-n)
-    double2 efrac[64];   // (e^{f/64}, e^{-f/64})
-    float2 eint32[64];   // the same, rounded to binary32 (binary32 rule)
-    float2 efrac32[64];
+    double2 eint[kKTabInt];   // (e^n, e^-n)
+    double2 efrac[64];        // (e^{f/64}, e^{-f/64})
+};
+struct KTab32 {
+    float2 eint[kKTabInt];
+    float2 efrac[64];
 };
 
 // Cooperative copy of the tables into LDS; every thread of the workgroup
 // must call it, before any evaluation of the K fallback.
-__device__ __forceinline__ void ktab_load(KTab *t) {
-    for (int i = threadIdx.x; i < 128; i += blockDim.x) {
-        const int j = i & 63;
-        if (i < 64) {
-            t->eint[j] = double2{tables::kExpInt64[j], tables::kExpNegInt64[j]};
-            t->eint32[j] = float2{float(tables::kExpInt64[j]), float(tables::kExpNegInt64[j])};
+template <typename Tab>
+__device__ __forceinline__ void ktab_load(Tab *t) {
+    using E = decltype(t->eint[0].x);
+    for (int i = threadIdx.x; i < kKTabInt + 64; i += blockDim.x) {
+        if (i < kKTabInt) {
+            t->eint[i] = {E(tables::kExpInt64[i]), E(tables::kExpNegInt64[i])};
         } else {
-            t->efrac[j] = double2{tables::kExpFrac64[j], tables::kExpNegFrac64[j]};
-            t->efrac32[j] = float2{float(tables::kExpFrac64[j]), float(tables::kExpNegFrac64[j])};
+            const int j = i - kKTabInt;
+            t->efrac[j] = {E(tables::kExpFrac64[j]), E(tables::kExpNegFrac64[j])};
         }
     }
     __syncthreads();
 }
 
-// The fallback's LDS tables by kind: e^{+-t} for K, log Gamma(1 + v) for I.
-template <int KIND> struct FbTabSel { using type = KTab; };
-template <> struct FbTabSel<KIND_I> { using type = LgTab; };
-template <int KIND> using FbTab = typename FbTabSel<KIND>::type;
+// The fallback's LDS tables by kind and precision: e^{+-t} for K, log
+// Gamma(1 + v) for I (both precisions' coefficients in one table).
+template <int KIND, typename T> struct FbTabSel {
+    using type = typename std::conditional<std::is_same<T, float>::value, KTab32, KTab>::type;
+};
+template <typename T> struct FbTabSel<KIND_I, T> { using type = LgTab; };
+template <int KIND, typename T> using FbTab = typename FbTabSel<KIND, T>::type;
 
 // Peak and step of the trapezoid rule on the cosh integral (both rules below).
 // peak: root t* > 0 of psi(t) = x sinh t - v tanh(v t) (convex on t >= 0,
@@ -733,7 +742,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     const double h = hq * kGrid;
     // shift M = log-integrand at t0 = t0q/64 in binary64 (log cosh(vt) =
     // vt + log1p(e^{-2vt}) - ln 2), e^{+-t0} from the node tables
-    const double2 pi0 = kt->eint[min(t0q >> 6, 63)];
+    const double2 pi0 = kt->eint[min(t0q >> 6, kKTabInt - 1)];
     const double2 pf0 = kt->efrac[t0q & 63];
     const double vt0 = v * (t0q * kGrid);
     const double M = fma(-0.5 * x, pi0.x * pf0.x + pi0.y * pf0.y, vt0) +
@@ -756,7 +765,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
             // e^{|t|}: a walk from t0 may step past t = 0, where the even
             // integrand is evaluated at its mirror node
             const int aq = abs(iq);
-            const double2 pi = kt->eint[min(aq >> 6, 63)];
+            const double2 pi = kt->eint[min(aq >> 6, kKTabInt - 1)];
             const double2 pf = kt->efrac[aq & 63];
             const double a = fma(-0.5 * x, pi.x * pf.x + pi.y * pf.y, -M);
             const double ap = fma(v, tj, a);
@@ -794,7 +803,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
 // the binary32 copies of the node tables, each term's exponential from the
 // hardware exp2 (its relative error grows with |exponent|, but so does the
 // term's smallness) and the r resets from the library expf.
-__device__ __forceinline__ float br_k_cosh32(float v, float x, const KTab *kt,
+__device__ __forceinline__ float br_k_cosh32(float v, float x, const KTab32 *kt,
                                              int *nodes = nullptr) {
     constexpr float kGrid = 1.0f / 64.0f;
     constexpr float kDrop = 18.0f;
@@ -802,8 +811,8 @@ __device__ __forceinline__ float br_k_cosh32(float v, float x, const KTab *kt,
     int t0q, hq;
     k_peak_step(v, x, v * v > x, 0.44f, 1.0f, t0q, hq);
     const float h = float(hq) * kGrid;
-    const float2 pi0 = kt->eint32[min(t0q >> 6, 63)];
-    const float2 pf0 = kt->efrac32[t0q & 63];
+    const float2 pi0 = kt->eint[min(t0q >> 6, kKTabInt - 1)];
+    const float2 pf0 = kt->efrac[t0q & 63];
     const float vt0 = v * (float(t0q) * kGrid);
     const float M = fmaf(-0.5f * x, pi0.x * pf0.x + pi0.y * pf0.y, vt0) +
                     logf(1.0f + expf(-2.0f * vt0)) - Cst<float>::ln2;
@@ -816,8 +825,8 @@ __device__ __forceinline__ float br_k_cosh32(float v, float x, const KTab *kt,
             if (((j - j0) & 15) == 0)
                 r = expf(-2.0f * v * tj);
             const int aq = abs(iq);
-            const float2 pi = kt->eint32[min(aq >> 6, 63)];
-            const float2 pf = kt->efrac32[aq & 63];
+            const float2 pi = kt->eint[min(aq >> 6, kKTabInt - 1)];
+            const float2 pf = kt->efrac[aq & 63];
             const float a = fmaf(-0.5f * x, pi.x * pf.x + pi.y * pf.y, -M);
             const float ap = fmaf(v, tj, a);
             const float ep = fm::exp_hw(ap);
@@ -981,12 +990,12 @@ __device__ __forceinline__ T order01(T x) {
 // Dispatch
 // ---------------------------------------------------------------------------
 
-// Value of the given branch.  binary32 computes in binary32 except the K
-// fallback, which runs in binary64 for both precisions.  K fallback: the
-// cosh-integral trapezoid for x >= 1e-10; below, the two-term small-argument
-// form (v < 0.3) or the 600-node rule on the u-integral of the paper.
+// Value of the given branch, in the precision T, except the K fallback below
+// x = 1e-10 (binary64 for both precisions).  K fallback: the cosh-integral
+// trapezoid for x >= 1e-10; below, the two-term small-argument form (v < 0.3)
+// or the 600-node rule on the u-integral of the paper.
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
-__device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND> *kt) {
+__device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND, T> *kt) {
     if (VAR == VAR_SEVEN) {
         switch (b) {
         case B7_MU3: return br_mu<T, KIND, 3>(v, x);

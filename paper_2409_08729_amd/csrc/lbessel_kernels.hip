@@ -114,7 +114,7 @@ __device__ __forceinline__ T combine(T v, T x, T g, T p, T y0, T y1) {
 
 // One evaluation that may still hit a special value (the v + 1 order).
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
-__device__ __forceinline__ T eval_full(T v, T x, const FbTab<KIND> *kt) {
+__device__ __forceinline__ T eval_full(T v, T x, const FbTab<KIND, T> *kt) {
     T y;
     if (special_value<T, KIND>(v, x, &y))
         return y;
@@ -124,24 +124,24 @@ __device__ __forceinline__ T eval_full(T v, T x, const FbTab<KIND> *kt) {
 // LDS copy of the fallback's tables (K: e^{+-t}; I: log Gamma(1 + v)), loaded
 // by every workgroup before its first evaluation (all threads must reach the
 // call).
-template <int KIND>
-__device__ __forceinline__ FbTab<KIND> *fb_tab_storage() {
-    __shared__ FbTab<KIND> kt;
+template <int KIND, typename T>
+__device__ __forceinline__ FbTab<KIND, T> *fb_tab_storage() {
+    __shared__ FbTab<KIND, T> kt;
     return &kt;
 }
 
-template <int KIND>
-__device__ __forceinline__ void fb_tab_load(FbTab<KIND> *kt) {
+template <int KIND, typename T>
+__device__ __forceinline__ void fb_tab_load(FbTab<KIND, T> *kt) {
     if constexpr (KIND == KIND_K)
         ktab_load(kt);
     else
         lgtab_load(kt);
 }
 
-template <int KIND>
-__device__ __forceinline__ const FbTab<KIND> *ktab_for_kind() {
-    FbTab<KIND> *kt = fb_tab_storage<KIND>();
-    fb_tab_load<KIND>(kt);
+template <int KIND, typename T>
+__device__ __forceinline__ const FbTab<KIND, T> *ktab_for_kind() {
+    FbTab<KIND, T> *kt = fb_tab_storage<KIND, T>();
+    fb_tab_load<KIND, T>(kt);
     return kt;
 }
 
@@ -150,7 +150,7 @@ __device__ __forceinline__ const FbTab<KIND> *ktab_for_kind() {
 // ---------------------------------------------------------------------------
 template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
-    const auto *kt = ktab_for_kind<KIND>();
+    const auto *kt = ktab_for_kind<KIND, T>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= a.n)
         return;
@@ -214,7 +214,7 @@ template <typename T, int NV, int NC, bool STAGE> struct Smem {
     T sv[STAGE ? TileCfg<NV>::tile : 1];                 // order, then result
     T sx[STAGE ? TileCfg<NV>::tile : 1];                 // argument
     uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, class-sorted
-    int cnt[NC][TileCfg<NV>::slots][kWaves];             // counts, then offsets
+    uint16_t cnt[NC][TileCfg<NV>::slots][kWaves];        // counts, then offsets
     int start[NC];                                       // first list position per class
     int n_fb, n_fb_u, n_all;                             // list segment ends
     uint32_t wmask[kWaves];                              // classes present, per wave
@@ -245,7 +245,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     __shared__ Smem<T, NV, NC, STAGE> sm;
 
     // the fallback's tables, loaded below only if the tile has fallback work
-    FbTab<KIND> *kt = fb_tab_storage<KIND>();
+    FbTab<KIND, T> *kt = fb_tab_storage<KIND, T>();
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -344,7 +344,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             return;   // every element was special or out of range (already stored)
         const int cls = __builtin_ctz(tile_mask);
         if (cls >= C::f0)
-            fb_tab_load<KIND>(kt);
+            fb_tab_load<KIND, T>(kt);
         const int b = (cls >= C::f0) ? BR_FB : (cls >= C::u0 ? BR_U : BR_MU);
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
@@ -397,7 +397,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     const int n_fb_u = sm.n_fb_u;                 // ... plus Debye
     const int n_all = sm.n_all;
     if (n_fb > 0)                                 // workgroup-uniform
-        fb_tab_load<KIND>(kt);
+        fb_tab_load<KIND, T>(kt);
 
     // 3. scatter evaluation ids in list order
 #pragma unroll
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void k_sorted_eval(const uint8_t *__restr
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ x,
                                                           double *__restrict__ out, int64_t n) {
-    const auto *kt = ktab_for_kind<KIND>();
+    const auto *kt = ktab_for_kind<KIND, double>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, u
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int32_t *nodes,
                                                      int64_t n) {
-    const KTab *kt = ktab_for_kind<KIND_K>();
+    const auto *kt = ktab_for_kind<KIND_K, T>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_branch(int b, const double *v, const double *x,
                                                      double *out, int64_t n) {
-    const auto *kt = ktab_for_kind<KIND>();
+    const auto *kt = ktab_for_kind<KIND, double>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
