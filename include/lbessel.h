@@ -252,7 +252,10 @@ int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
  * Evaluate every element with one forced branch (0, 1 or 2 as above)
  * regardless of its regime, f64 only.  Used to validate each branch
  * against the reference on its own; outside a branch's regime the result is
- * simply that expansion's value, which may be inaccurate.
+ * simply that expansion's value, which may be inaccurate.  The K fallback's
+ * integration grid covers t < 32, which every element of its own region
+ * (x >= 1e-10, v <= 16) stays inside; a forced fallback far outside it
+ * (orders of thousands at x ~ 1e-10) is not meaningful.
  */
 int lbessel_eval_branch_f64(int kind, int branch, const double *v,
                             const double *x, double *out, int64_t n,
