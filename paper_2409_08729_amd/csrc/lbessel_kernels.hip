@@ -15,9 +15,9 @@
 //   3. the list is cut into 64-entry chunks that the wavefronts take from an
 //      LDS counter, so a wavefront runs one class except in the chunks that
 //      straddle two, and expensive chunks spread over the four wavefronts;
-//   4. results go straight to HBM, or (log K, whose pairs are staged in LDS)
-//      into LDS and out in one coalesced store, or into LDS to be combined
-//      per element (two orders per element).
+//   4. results go straight to HBM, or (one-order K, and I in binary32, whose
+//      pairs are staged in LDS) into LDS and out in one coalesced store, or
+//      into LDS to be combined per element (two orders per element).
 // The branch of an evaluation depends only on its own (v, x), never on its
 // neighbours, so the grouped and the ungrouped kernel give the same bits.
 #include <hip/hip_runtime.h>
@@ -204,12 +204,15 @@ template <int KIND, int OP, int VAR> struct Classes {
     static constexpr int none = (1 << bits) - 1;
 };
 
-// K forward (STAGE): the tile's (order, argument) pairs are staged in LDS in
-// step 1 and the results in the order slots in step 4, so HBM sees one
-// coalesced read of (v, x) and one coalesced write of the results per
-// element, however long the tile's integrals take.  Other operations finish
-// a tile quickly enough that the step-4 re-reads hit L2, and they skip the
-// extra LDS traffic.
+// One-order operations of K, and of I in binary32 (STAGE): the tile's (order,
+// argument) pairs are staged in LDS in step 1 and the results in the order
+// slots in step 4, so HBM sees one coalesced read of (v, x) and one coalesced
+// write of the results per element, however long the tile's integrals take,
+// and step 4 reads its operands from LDS instead of waiting on L2.  The
+// binary64 I kernels do without: their 16 KB of staging would cut them from
+// 8 workgroups per CU to 6, which costs more than the L2 re-reads.  The
+// two-order operations finish a tile quickly enough that the step-4 re-reads
+// hit L2.
 template <typename T, int NV, int NC, bool STAGE> struct Smem {
     T sv[STAGE ? TileCfg<NV>::tile : 1];                 // order, then result
     T sx[STAGE ? TileCfg<NV>::tile : 1];                 // argument
@@ -241,7 +244,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     constexpr uint32_t MASK = (1u << BITS) - 1;
     static_assert(SLOTS * BITS <= 32, "class codes of one thread fit 32 bits");
     static_assert(NC * SLOTS <= 64, "one lane clears each (class, slot) count");
-    constexpr bool STAGE = (NV == 1) && (KIND == KIND_K);
+    constexpr bool STAGE = (NV == 1) && (KIND == KIND_K || sizeof(T) == 4);
     __shared__ Smem<T, NV, NC, STAGE> sm;
 
     // the fallback's tables, loaded below only if the tile has fallback work
