@@ -258,16 +258,23 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     //    (slot = r * NV + sub), C::none = nothing to evaluate.
     uint32_t code = 0;
     uint32_t done = 0;   // bit r: element r finished in this step (or out of range)
+    // unstaged kernels keep the loaded operands for a one-class tile, which
+    // then evaluates without a second (L2) read
+    T vr[EPT], xr[EPT];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
         const int e = r * kThreads + tid;
         const int64_t i = base + e;
         int b0 = C::none, b1 = C::none;
+        vr[r] = T(0);
+        xr[r] = T(1);
         if (i >= a.n) {
             done |= 1u << r;
         } else {
             const T v = order_of<T, KIND, OP>(a, i);
             const T x = a.x[i];
+            vr[r] = v;
+            xr[r] = x;
             T res;
             const T g = (a.g != nullptr) ? a.g[i] : T(1);
             if (element_special<T, KIND, OP>(v, x, g, a.p, &res)) {
@@ -354,8 +361,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             if (done & (1u << r))
                 continue;
             const int e = r * kThreads + tid;
-            const T v = STAGE ? sm.sv[e] : order_of<T, KIND, OP>(a, base + e);
-            const T x = STAGE ? sm.sx[e] : a.x[base + e];
+            const T v = STAGE ? sm.sv[e] : vr[r];
+            const T x = STAGE ? sm.sx[e] : xr[r];
             const T y = eval_branch<T, KIND, VAR>(b, v, x, kt);
             a.out[base + e] = combine<T, KIND, OP>(v, x, T(1), a.p, y, y);
         }
