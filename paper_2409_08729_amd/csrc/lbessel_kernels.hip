@@ -259,7 +259,10 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     uint32_t code = 0;
     uint32_t done = 0;   // bit r: element r finished in this step (or out of range)
     // unstaged kernels keep the loaded operands for a one-class tile, which
-    // then evaluates without a second (L2) read
+    // then evaluates without a second (L2) read; the measurement variants,
+    // whose branch code needs more registers, read again instead (kept, the
+    // operands would cost them a wave per SIMD)
+    constexpr bool KEEP = (VAR == VAR_DEFAULT);
     T vr[EPT], xr[EPT];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
@@ -361,8 +364,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             if (done & (1u << r))
                 continue;
             const int e = r * kThreads + tid;
-            const T v = STAGE ? sm.sv[e] : vr[r];
-            const T x = STAGE ? sm.sx[e] : xr[r];
+            const T v = STAGE ? sm.sv[e] : KEEP ? vr[r] : order_of<T, KIND, OP>(a, base + e);
+            const T x = STAGE ? sm.sx[e] : KEEP ? xr[r] : a.x[base + e];
             const T y = eval_branch<T, KIND, VAR>(b, v, x, kt);
             a.out[base + e] = combine<T, KIND, OP>(v, x, T(1), a.p, y, y);
         }
