@@ -38,27 +38,27 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPMODEL = os.path.join(ROOT, "paper_2409_08729_amd", "opmodel.json")
 
 
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_log_kv_f64_stress.json")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_hot_path.json")
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def traffic_per_launch():
-    """HBM bytes of one stress-grid log K launch from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel sources changed
-    since those counters were taken."""
+def counters(label: str):
+    """Counter record of one launch from the committed probe summary
+    (counter_probe.py), or None if the kernel sources changed since the
+    counters were taken (or the launch was not probed)."""
     import hashlib
-    if not os.path.exists(TRAFFIC):
+    if not os.path.exists(COUNTERS):
         return None
-    t = json.load(open(TRAFFIC))
+    t = json.load(open(COUNTERS))
     h = hashlib.sha256()
     for src in t["sources"]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest() != t["source_sha256"]:
         return None
-    return t["hbm_bytes_per_launch"]
+    return t["launches"].get(label)
 
 
 def make_inputs(torch, dev):
@@ -95,7 +95,7 @@ def op_counts(lb, torch, sets):
     term-count tier) and the total integrand node count of the K fallback
     elements (lbessel_k_nodes) for the op model."""
     mix, nodes = {}, {}
-    cuts = torch.tensor(U_TIER_CUTS, dtype=torch.float64, device=sets[0][1].device)
+    cuts = torch.tensor(U_TIER_CUTS, dtype=sets[0][1].dtype, device=sets[0][1].device)
     for j, (name, v, x) in enumerate(sets):
         for kind in ("I", "K"):
             b = lb.classify(kind, v, x).to(torch.int64)
@@ -143,32 +143,63 @@ def cpu_baseline(sets_host, seconds_target=12.0):
     return rec, sample
 
 
+def _err_record(v, x, y, hi, lo, tol, kind, deriv=None):
+    """Error measures of outputs y against the oracle (hi + lo) at (v, x):
+    the parity measure |y - ref| / max(|ref|, 1 + |(v, x)|), the plain relative
+    error |y - ref| / |ref| and rel_floor1 = |y - ref| / max(|ref|, 1), with
+    decade histograms, and every point whose plain relative error exceeds tol
+    listed with |ref|, |(v, x)| and its distance to the nearest zero of the
+    log-value in relative x, |ref / (x d ref/dx)| (first order; deriv gives
+    the oracle's d/dx at the listed points)."""
+    fin = np.isfinite(hi)
+    v, x, y, hi, lo = v[fin], x[fin], y[fin], hi[fin], lo[fin]
+    d = np.abs((y - hi) - lo)
+    cond = d / np.maximum(np.abs(hi), 1.0 + np.hypot(v, x))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(hi != 0, d / np.abs(hi), 0.0)
+    floor1 = d / np.maximum(np.abs(hi), 1.0)
+    above = np.nonzero(rel > tol)[0]
+    listing = []
+    if above.size:
+        above = above[np.argsort(-rel[above])]
+        dh = deriv(v[above], x[above])[0] if deriv is not None else np.full(above.size, np.nan)
+        for k, dk in zip(above, dh):
+            listing.append({"v": float(v[k]), "x": float(x[k]), "abs_y": float(abs(hi[k])),
+                            "norm_vx": float(np.hypot(v[k], x[k])), "rel_err": float(rel[k]),
+                            "cond_err": float(cond[k]), "rel_floor1": float(floor1[k]),
+                            "zero_dist_rel_x": float(abs(hi[k] / (x[k] * dk)))})
+    return {"kind": kind, "points": int(fin.sum()), "max_cond_err": float(cond.max(initial=0.0)),
+            "max_rel_err": float(rel.max(initial=0.0)),
+            "max_rel_floor1": float(floor1.max(initial=0.0)),
+            "hist_cond_err": histogram(cond), "hist_rel_err": histogram(rel),
+            "hist_rel_floor1": histogram(floor1), "rel_err_tol": tol,
+            "above_tol": len(listing),
+            "above_tol_max_abs_y_over_scale": max(
+                (p["abs_y"] / (1.0 + p["norm_vx"]) for p in listing), default=None),
+            "above_tol_max_zero_dist_rel_x": max(
+                (p["zero_dist_rel_x"] for p in listing), default=None),
+            "above_tol_points": listing}
+
+
 def sample_errors(torch, outs, sample):
-    """Largest error of the timed step's f64 outputs on the oracle sample:
-    |y - ref| / max(|ref|, 1 + |(v, x)|) (the parity measure) and the plain
-    relative error |y - ref| / |ref|, per function."""
+    """Errors of the timed step's f64 outputs on the oracle sample, per
+    function (_err_record with the binary64 target 4e-15)."""
+    from oracle import oracle
     res = {}
     for kind, col in (("I", 3), ("K", 4)):
-        worst_c, worst_r, npts = 0.0, 0.0, 0
-        all_c, all_r = [], []
+        vs, xs, ys, his, los = [], [], [], [], []
         for blk in sample:
             ids, v, x = blk[0], blk[1], blk[2]
             hi, lo = blk[col]
-            got = np.concatenate([outs[(j, kind)][torch.from_numpy(idx).to(outs[(j, kind)].device)]
-                                  .cpu().numpy() for j, idx in ids])
-            fin = np.isfinite(hi)
-            d = np.abs((got[fin] - hi[fin]) - lo[fin])
-            den = np.maximum(np.abs(hi[fin]), 1.0 + np.hypot(v[fin], x[fin]))
-            worst_c = max(worst_c, float((d / den).max(initial=0.0)))
-            with np.errstate(divide="ignore", invalid="ignore"):
-                rel = np.where(hi[fin] != 0, d / np.abs(hi[fin]), 0.0)
-            worst_r = max(worst_r, float(rel.max(initial=0.0)))
-            npts += int(fin.sum())
-            all_c.append(d / den)
-            all_r.append(rel)
-        res[kind] = {"max_cond_err": worst_c, "max_rel_err": worst_r, "points": npts,
-                     "hist_cond_err": histogram(np.concatenate(all_c)),
-                     "hist_rel_err": histogram(np.concatenate(all_r))}
+            ys.append(np.concatenate([outs[(j, kind)][torch.from_numpy(idx).to(outs[(j, kind)].device)]
+                                      .cpu().numpy() for j, idx in ids]))
+            vs.append(v)
+            xs.append(x)
+            his.append(hi)
+            los.append(lo)
+        res[kind] = _err_record(np.concatenate(vs), np.concatenate(xs), np.concatenate(ys),
+                                np.concatenate(his), np.concatenate(los), 4e-15, kind,
+                                oracle.dlog_iv if kind == "I" else oracle.dlog_kv)
     return res
 
 
@@ -237,29 +268,26 @@ def histogram(err):
 
 def f32_errors(torch, sets32, outs32, per_set=1 << 11):
     """Per-result error of the timed binary32 outputs against the oracle at the
-    binary32 inputs (widened exactly), on a seeded sample of every set: the
-    parity measure |y - ref| / max(|ref|, 1 + |(v, x)|) and the plain
-    relative error, with their decade histograms."""
+    binary32 inputs (widened exactly), on a seeded sample of every set
+    (_err_record with the binary32 target 2e-6)."""
     from oracle import oracle
     rng = np.random.default_rng(6)
     res = {}
     for kind in ("I", "K"):
-        cond, rel = [], []
+        vs, xs, ys, his, los = [], [], [], [], []
         for j, (name, v, x) in enumerate(sets32):
             idx = torch.from_numpy(rng.integers(0, v.numel(), per_set)).to(v.device)
             hv = v[idx].double().cpu().numpy()
             hx = x[idx].double().cpu().numpy()
-            y = outs32[(j, kind)][idx].double().cpu().numpy()
+            ys.append(outs32[(j, kind)][idx].double().cpu().numpy())
             hi, lo = (oracle.log_iv if kind == "I" else oracle.log_kv)(hv, hx)
-            fin = np.isfinite(hi)
-            d = np.abs((y[fin] - hi[fin]) - lo[fin])
-            cond.append(d / np.maximum(np.abs(hi[fin]), 1.0 + np.hypot(hv[fin], hx[fin])))
-            with np.errstate(divide="ignore", invalid="ignore"):
-                rel.append(np.where(hi[fin] != 0, d / np.abs(hi[fin]), 0.0))
-        cond, rel = np.concatenate(cond), np.concatenate(rel)
-        res[kind] = {"points": int(cond.size), "max_cond_err": float(cond.max()),
-                     "max_rel_err": float(rel.max()), "hist_cond_err": histogram(cond),
-                     "hist_rel_err": histogram(rel)}
+            vs.append(hv)
+            xs.append(hx)
+            his.append(hi)
+            los.append(lo)
+        res[kind] = _err_record(np.concatenate(vs), np.concatenate(xs), np.concatenate(ys),
+                                np.concatenate(his), np.concatenate(los), 2e-6, kind,
+                                oracle.dlog_iv if kind == "I" else oracle.dlog_kv)
     return {"sample": f"{per_set} seeded points per set at the binary32 inputs", **res}
 
 
@@ -497,6 +525,8 @@ def main():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-tables", action="store_true",
                     help="skip the order-0/1 and paper runtime-table workloads")
+    ap.add_argument("--detail", default=None,
+                    help="also write the detail record (indented JSON) to this file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -533,56 +563,23 @@ def main():
         per.setdefault((name, kind), []).append(e0.elapsed_time(e1))
     finite = all(torch.isfinite(o).all().item() for o in outs.values())
 
-    # roofline of the dominant kernel: log K f64, on its largest launch (the
-    # stress grid); op model = per-branch VALU instructions x branch counts
     mix, knodes = op_counts(lb, torch, sets)
     om = json.load(open(OPMODEL))
-    ck = om["K_f64"]
-
-    def k_ops(j):
-        c = mix[(j, "K")]
-        return (c["mu20"] * ck["mu20"] + sum(c[u] * ck[u] for u in ("u13", "u9", "u6", "u4"))
-                + c["fallback"] * ck["fallback_setup"] + knodes[j] * ck["fallback_per_node"])
-
+    kern, ops64 = launch_table(per, sets, mix, knodes, om, "f64")
     js = len(sets) - 1
-    ops = k_ops(js)
-    dur = float(np.mean(per[(sets[js][0], "K")])) * 1e-3
-    achieved = ops / dur / 1e12
-    all_ops = sum(k_ops(j) for j in range(len(sets)))
-    all_dur = sum(float(np.mean(per[(nm, "K")])) for nm, _, _ in sets) * 1e-3
-    roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic_per_launch(),
-            "kernel": "k_grouped<double, K, log> (lbessel_log_kv_f64)",
-            "launch": f"{sets[js][0]}: {sets[js][1].numel()} pairs",
-            "ops_per_launch": ops, "launch_ms": dur * 1e3,
-            "branch_counts": mix[(js, "K")],
-            "fallback_nodes": knodes[js],
-            "op_model": "mu20 x n_mu + sum over Debye tiers uK x n_uK + fallback_setup x n_fb"
-                        " + fallback_per_node x nodes (paper_2409_08729_amd/opmodel.json)",
-            "algorithmic_bytes_per_launch": 24 * sets[js][1].numel(),
-            "all_K_launches": {"frac": all_ops / all_dur / 1e12 / VALU_PEAK_TOPS,
-                               "ms": all_dur * 1e3}}
-
-    ci = om["I_f64"]
-
-    def i_ops(j):
-        c = mix[(j, "I")]
-        return (c["mu20"] * ci["mu20"] + sum(c[u] * ci[u] for u in ("u13", "u9", "u6", "u4"))
-                + c["fallback"] * ci["fallback"])
-
-    kern = {}
-    for (name, kind), ts in per.items():
-        j = [i for i, (nm, _, _) in enumerate(sets) if nm == name][0]
-        n = sets[j][1].numel()
-        ops_j = k_ops(j) if kind == "K" else i_ops(j)
-        kern[f"{kind}:{name}"] = {"ms": float(np.mean(ts)), "G_evals_s": n / np.mean(ts) / 1e6,
-                                  "valu_frac": ops_j / (float(np.mean(ts)) * 1e-3) / 1e12
-                                  / VALU_PEAK_TOPS}
-    roof["per_launch_note"] = ("kernels[...].valu_frac: op-model VALU work / launch time / peak for "
-                               "every launch; the I series is charged its cost at v = 3, x = 5 "
-                               "(exact for launches without series elements, v >= 2^4)")
-    i_ms = sum(np.mean(ts) for (nm, kd), ts in per.items() if kd == "I")
-    k_ms = sum(np.mean(ts) for (nm, kd), ts in per.items() if kd == "K")
+    stress = sets[js][0]
+    roof = roofline_block(ops64[(js, "K")], kern[f"K:{stress}"]["ms"],
+                          "k_grouped<double, K, log> (lbessel_log_kv_f64)",
+                          f"{stress}: {sets[js][1].numel()} pairs", sets[js][1].numel(), 24,
+                          "log_kv_f64_stress")
+    roof["branch_counts"] = mix[(js, "K")]
+    roof["fallback_nodes"] = knodes[js]
+    all_k_ops = sum(ops64[(j, "K")] for j in range(len(sets)))
+    all_k_ms = sum(kern[f"K:{nm}"]["ms"] for nm, _, _ in sets)
+    roof["all_K_launches"] = {"frac": all_k_ops / (all_k_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                              "ms": all_k_ms}
+    i_ms = sum(kern[f"I:{nm}"]["ms"] for nm, _, _ in sets)
+    k_ms = all_k_ms
 
     # grouping ablation: the same launches without regrouping by branch
     ablation = {}
@@ -597,7 +594,7 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             ung = e0.elapsed_time(e1)
-            grp = float(np.mean(per[(name, kind)]))
+            grp = kern[f"{kind}:{name}"]["ms"]
             ablation[f"{kind}:{name}"] = {"grouped_ms": grp, "ungrouped_ms": ung,
                                           "speedup": ung / grp}
 
@@ -607,11 +604,28 @@ def main():
         o32 = {}
         one_step(lb, torch, sets32, o32)
         torch.cuda.synchronize()
+        timers32 = []
+        steps32 = max(args.steps, 3)
         t = time.perf_counter()
-        one_step(lb, torch, sets32, o32)
+        for _ in range(steps32):
+            one_step(lb, torch, sets32, o32, timers32)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        f32 = {"value": evals / dt / 1e9, "unit": "G evals/s", "ms_per_step": dt * 1e3}
+        dt = (time.perf_counter() - t) / steps32
+        per32 = {}
+        for name, kind, e0, e1 in timers32:
+            per32.setdefault((name, kind), []).append(e0.elapsed_time(e1))
+        mix32, knodes32 = op_counts(lb, torch, sets32)
+        kern32, ops32 = launch_table(per32, sets32, mix32, knodes32, om, "f32")
+        f32 = {"value": evals / dt / 1e9, "unit": "G evals/s", "ms_per_step": dt * 1e3,
+               "steps": steps32, "kernels": kern32}
+        if ops32 is not None:
+            f32["roofline"] = roofline_block(
+                ops32[(js, "K")], kern32[f"K:{stress}"]["ms"],
+                "k_grouped<float, K, log> (lbessel_log_kv_f32)",
+                f"{stress}: {sets[js][1].numel()} pairs", sets[js][1].numel(), 12,
+                "log_kv_f32_stress")
+            f32["roofline"]["branch_counts"] = mix32[(js, "K")]
+            f32["roofline"]["fallback_nodes"] = knodes32[js]
         if not args.no_cpu_baseline:
             f32["errors"] = f32_errors(torch, sets32, o32)
         del sets32, o32
@@ -619,6 +633,20 @@ def main():
     ablations = None
     if not args.no_ablation:
         ablations = ablation_bench(lb, torch, sets)
+    paper_k = None
+    if ablations is not None and "quad600_per_eval" in om.get("K_f64", {}):
+        # the paper's own K fallback (eq. log Kv integral, 600 nodes; u_integral
+        # variant, Debye at 13 terms everywhere) on the stress grid
+        c = mix[(js, "K")]
+        ck = om["K_f64"]
+        ops = (c["mu20"] * ck["mu20"] + (c["u13"] + c["u9"] + c["u6"] + c["u4"]) * ck["u13"]
+               + c["fallback"] * ck["quad600_per_eval"])
+        ms = ablations["results"]["u_integral/grouped"]["K"][f"{stress}_ms"]
+        paper_k = roofline_block(ops, ms, "k_grouped<double, K, log, u_integral> "
+                                 "(lbessel_eval_variant u_integral, grouped)",
+                                 f"{stress}: {sets[js][1].numel()} pairs", sets[js][1].numel(),
+                                 24, "log_kv_f64_stress_u_integral")
+        paper_k["quad600_per_eval"] = ck["quad600_per_eval"]
     order01, paper_tables = None, None
     if not args.no_tables:
         log("orders 0/1 and the paper's runtime tables")
@@ -643,6 +671,32 @@ def main():
         torch.cuda.empty_cache()
         serving = serving_bench(torch)
 
+    workload = ("log I_v and log K_v, f64: 20M pairs per order v=2^0..2^10 with x~U[1,100) "
+                "plus the 2^26-pair stress grid (log10 v~U[-3,4], log10 x~U[-4,4])")
+    detail = {
+        "what": "bench detail (the last line is the summary)",
+        "config": {"workload": workload, "pairs_per_step": n_pairs, "evals_per_step": evals},
+        "roofline": roof, "cpu_baseline": cpu, "all_finite": finite,
+        "max_err_on_oracle_sample": errors, "ms_I_per_step": i_ms, "ms_K_per_step": k_ms,
+        "f32": f32, "paper_k": paper_k, "grouping_ablation": ablation, "ablations": ablations,
+        "order01": order01, "paper_tables": paper_tables, "vmf": vmf_res, "serving": serving,
+        "kernels": kern,
+    }
+    if args.detail:
+        with open(args.detail, "w") as f:
+            json.dump(detail, f, indent=1)
+    print(json.dumps(detail), flush=True)
+
+    def errsum(e):
+        if e is None:
+            return None
+        return {k: {"points": e[k]["points"], "max_cond_err": e[k]["max_cond_err"],
+                    "max_rel_err": e[k]["max_rel_err"], "max_rel_floor1": e[k]["max_rel_floor1"],
+                    "above_tol": e[k]["above_tol"]} for k in ("I", "K")}
+
+    keep = ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel", "launch",
+            "launch_ms", "ops_per_launch", "algorithmic_bytes_per_launch", "valu_busy",
+            "active_lanes")
     line = {
         "metric": "G evals/s log I_v & log K_v (f64, f32) at max rel err; "
                   "p50/p99 latency at QPS",
@@ -657,26 +711,75 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "log I_v and log K_v, f64: 20M pairs per order v=2^0..2^10 with "
-                               "x~U[1,100) plus 2^26-pair stress grid (log10 v~U[-3,4], "
-                               "log10 x~U[-4,4])",
-                   "pairs_per_step": n_pairs, "evals_per_step": evals},
-        "roofline": roof,
+        "config": {"workload": workload, "pairs_per_step": n_pairs, "evals_per_step": evals},
+        "roofline": {k: roof[k] for k in keep if k in roof} | {
+            "all_K_launches_frac": roof["all_K_launches"]["frac"]},
         "cpu_baseline": cpu,
         "all_finite": finite,
-        "max_err_on_oracle_sample": errors,
+        "errors": errsum(errors),
         "ms_I_per_step": i_ms,
         "ms_K_per_step": k_ms,
-        "f32": f32,
-        "grouping_ablation": ablation,
-        "ablations": ablations,
-        "order01": order01,
-        "paper_tables": paper_tables,
-        "vmf": vmf_res,
-        "serving": serving,
-        "kernels": kern,
+        "f32": None if f32 is None else {
+            "value": f32["value"], "unit": "G evals/s", "ms_per_step": f32["ms_per_step"],
+            "roofline": None if "roofline" not in f32 else {
+                k: f32["roofline"][k] for k in keep if k in f32["roofline"]},
+            "errors": errsum(f32.get("errors"))},
+        "paper_k_u_integral": None if paper_k is None else {
+            k: paper_k[k] for k in ("launch_ms", "frac", "valu_busy", "active_lanes")
+            if k in paper_k},
+        "serving_saturation_req_s": None if serving is None else {
+            k: v["requests_per_s"] for k, v in serving["saturation"].items()},
     }
     print(json.dumps(line), flush=True)
+
+
+def launch_table(per, sets, mix, knodes, om, prec):
+    """Per-launch time, G evals/s and op-model VALU fraction, and the
+    algorithmic ops of every launch ((set, kind) -> ops; None without an op
+    model for this precision)."""
+    ck, ci = om.get(f"K_{prec}"), om.get(f"I_{prec}")
+    ops = None
+    if ck is not None and ci is not None:
+        ops = {}
+        for j in range(len(sets)):
+            c = mix[(j, "K")]
+            ops[(j, "K")] = (c["mu20"] * ck["mu20"]
+                             + sum(c[u] * ck[u] for u in ("u13", "u9", "u6", "u4"))
+                             + c["fallback"] * ck["fallback_setup"]
+                             + knodes[j] * ck["fallback_per_node"])
+            c = mix[(j, "I")]
+            ops[(j, "I")] = (c["mu20"] * ci["mu20"]
+                             + sum(c[u] * ci[u] for u in ("u13", "u9", "u6", "u4"))
+                             + c["fallback"] * ci["fallback"])
+    kern = {}
+    for (name, kind), ts in per.items():
+        j = [i for i, (nm, _, _) in enumerate(sets) if nm == name][0]
+        n = sets[j][1].numel()
+        ms = float(np.mean(ts))
+        kern[f"{kind}:{name}"] = {"ms": ms, "G_evals_s": n / ms / 1e6}
+        if ops is not None:
+            kern[f"{kind}:{name}"]["valu_frac"] = ops[(j, kind)] / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+    return kern, ops
+
+
+def roofline_block(ops, ms, kernel, launch, n, bytes_per_pair, counter_label):
+    """Roofline record of one launch: algorithmic VALU lane-instructions (the
+    op model) per launch over its measured duration, against the VALU issue
+    rate; counters (traffic, VALU busy, active lanes) from the committed probe
+    summary while the kernel sources match it."""
+    achieved = ops / (ms * 1e-3) / 1e12
+    c = counters(counter_label)
+    rec = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+           "frac": achieved / VALU_PEAK_TOPS,
+           "traffic": None if c is None else c["hbm_bytes"],
+           "kernel": kernel, "launch": launch, "launch_ms": ms, "ops_per_launch": ops,
+           "algorithmic_bytes_per_launch": bytes_per_pair * n,
+           "op_model": "mu20 x n_mu + sum over Debye tiers uK x n_uK + fallback_setup x n_fb"
+                       " + fallback_per_node x nodes (paper_2409_08729_amd/opmodel.json)"}
+    if c is not None:
+        rec["valu_busy"] = c["valu_busy"]
+        rec["active_lanes"] = c["active_lanes"]
+    return rec
 
 
 if __name__ == "__main__":

@@ -8,10 +8,14 @@
  * "Algorithms", Table 1 and Algorithm 1 in its GPU form): the Hankel
  * expansion with 20 correction terms (eqs. log Iv mu k / log Kv mu k), the
  * Debye expansion with 13 terms (eqs. log Iv u k / log Kv u k), or, for small
- * arguments, the power series of I_v (eqs. Iv infinite series, log Iv) or the
- * integral representation of K_v (eq. log Kv integral).  All intermediate
- * quantities stay on a log scale, so results are finite wherever log I_v(x)
- * and log K_v(x) are.
+ * arguments, the power series of I_v (eqs. Iv infinite series, log Iv) or an
+ * integral of K_v.  The paper integrates its own representation (eq. log Kv
+ * integral, 600 nodes); this library's K fallback instead applies the
+ * trapezoid rule to K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF
+ * 10.32.9) for x >= 1e-10, and the leading terms of DLMF 10.27.4 below; the
+ * paper's integral stays available through lbessel_eval_variant.  All
+ * intermediate quantities stay on a log scale, so results are finite
+ * wherever log I_v(x) and log K_v(x) are.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -71,8 +75,14 @@ int lbessel_log_iv_f32(const float *v, const float *x, float *out,
                        int64_t n, void *stream);
 
 /*
- * out[i] = log K_{v[i]}(x[i]); same structure, with the integral
- * representation (eq. log Kv integral) as the small-argument branch.
+ * out[i] = log K_{v[i]}(x[i]); same structure.  Small-argument branch (the
+ * paper's fallback of Algorithm 1): for x >= 1e-10 the trapezoid rule on
+ * K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9), summed in
+ * log scale over the nodes within a fixed drop of the integrand's peak; for
+ * x < 1e-10 the two leading terms of K_v = pi (I_{-v} - I_v) / (2 sin v pi)
+ * (DLMF 10.27.4), rearranged for v < 0.3.  This replaces the paper's
+ * 600-node rule on its own integral (eq. log Kv integral), which
+ * lbessel_eval_variant keeps as LBESSEL_VAR_U_INTEGRAL / _SIMPSON / _PAPER.
  */
 int lbessel_log_kv_f64(const double *v, const double *x, double *out,
                        int64_t n, void *stream);
@@ -250,7 +260,7 @@ int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
 
 /*
  * Evaluate every element with one forced branch (0, 1 or 2 as above)
- * regardless of its regime, f64 only.  Used to validate each branch
+ * regardless of its regime.  Used to validate each branch
  * against the reference on its own; outside a branch's regime the result is
  * simply that expansion's value, which may be inaccurate.  The K fallback's
  * integration grid covers t < 32, which every element of its own region
@@ -259,6 +269,10 @@ int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
  */
 int lbessel_eval_branch_f64(int kind, int branch, const double *v,
                             const double *x, double *out, int64_t n,
+                            void *stream);
+/* The same in binary32 (the binary32 branches, thresholds not applied). */
+int lbessel_eval_branch_f32(int kind, int branch, const float *v,
+                            const float *x, float *out, int64_t n,
                             void *stream);
 
 /*

@@ -68,6 +68,7 @@ def _load():
         "lbessel_eval_variant": [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp,
                                  i64, vp],
         "lbessel_eval_branch_f64": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_eval_branch_f32": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_eval_ungrouped": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_vmf_colsum_f32": [vp, i64, i64, vp, vp, vp, i64, vp],
         "lbessel_vmf_fit_f32": [vp, i64, i64, vp, vp, i64, vp],
@@ -347,15 +348,13 @@ def k_nodes(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
 
 
 def eval_branch(kind: str, branch: int, v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-    """Every element through one forced branch (float64)."""
+    """Every element through one forced branch (float64 or float32)."""
     v, x = _prep(v, x)
-    if x.dtype != torch.float64:
-        raise LbesselError("eval_branch is float64 only")
     out = torch.empty_like(x)
+    fn = f"lbessel_eval_branch_{_suffix(x)}"
     with torch.cuda.device(x.device):
-        _check(_load().lbessel_eval_branch_f64(KIND[kind], int(branch), v.data_ptr(),
-                                               x.data_ptr(), out.data_ptr(), x.numel(),
-                                               _stream(x)), "lbessel_eval_branch_f64")
+        _check(getattr(_load(), fn)(KIND[kind], int(branch), v.data_ptr(), x.data_ptr(),
+                                    out.data_ptr(), x.numel(), _stream(x)), fn)
     return out
 
 

@@ -8,9 +8,15 @@
 //   series: power series of I_v summed in log scale, eqs. (Iv infinite
 //           series), (ak recurrence), (log Iv), truncated when the remaining
 //           terms fall below the working precision (text after eq. K);
-//   quad  : integral representation of K_v (eq. log Kv integral, n = 8) on
-//           the paper's N = 600 equispaced nodes, summed in log scale with
-//           the heuristic maxima u* = 1 for g and u* = 1/2 or 1/(2v) for h.
+//   K fallback (the library's path): for x >= 1e-10 the trapezoid rule on
+//           K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9)
+//           over the nodes within a fixed drop of the log-integrand's peak
+//           (br_k_cosh, br_k_cosh32); for x < 1e-10 the leading terms of
+//           DLMF 10.27.4 (br_k_tiny_x, br_k_small_x);
+//   quad  : the paper's own integral representation of K_v (eq. log Kv
+//           integral, n = 8) on its N = 600 equispaced nodes, summed in log
+//           scale with the heuristic maxima u* = 1 for g and u* = 1/2 or
+//           1/(2v) for h (br_quad_k; the measurement variants only).
 // Branch selection keeps the predicate shapes of Table 1 / Algorithm 1 (GPU
 // form: mu_20, then U_13, else the fallback) with thresholds re-fitted so
 // that each branch meets 1e-15 relative error on its region.
@@ -992,8 +998,9 @@ __device__ __forceinline__ T order01(T x) {
 
 // Value of the given branch, in the precision T, except the K fallback below
 // x = 1e-10 (binary64 for both precisions).  K fallback: the cosh-integral
-// trapezoid for x >= 1e-10; below, the two-term small-argument form (v < 0.3)
-// or the 600-node rule on the u-integral of the paper.
+// trapezoid for x >= 1e-10; below, the small-argument forms (br_k_tiny_x for
+// v < 0.3, br_k_small_x above).  The u-integral variants take the paper's
+// 600-node rule for x >= 1e-10 and for x < 1e-10 with v >= 0.3.
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
 __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND, T> *kt) {
     if (VAR == VAR_SEVEN) {

@@ -620,17 +620,17 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
     nodes[i] = c;
 }
 
-template <int KIND>
-__global__ __launch_bounds__(kThreads) void k_branch(int b, const double *v, const double *x,
-                                                     double *out, int64_t n) {
-    const auto *kt = ktab_for_kind<KIND, double>();
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_branch(int b, const T *v, const T *x, T *out,
+                                                     int64_t n) {
+    const auto *kt = ktab_for_kind<KIND, T>();
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
-    const double vv = (KIND == KIND_K) ? fabs(v[i]) : v[i];
-    double y;
-    if (!special_value<double, KIND>(vv, x[i], &y))
-        y = eval_branch<double, KIND>(b, vv, x[i], kt);
+    const T vv = (KIND == KIND_K) ? fabs(v[i]) : v[i];
+    T y;
+    if (!special_value<T, KIND>(vv, x[i], &y))
+        y = eval_branch<T, KIND>(b, vv, x[i], kt);
     out[i] = y;
 }
 
@@ -767,9 +767,13 @@ __global__ __launch_bounds__(kThreads) void k_sumsq(const double *__restrict__ c
 // same branch code as the forward path, until the step is below 1e-15
 // relative or no longer shrinks (the noise floor of A_p, whose two log-values
 // are of size ~kappa), at most 40 steps.  One lane; out = {kappa, R, kappa_0,
-// steps}.
+// steps}.  The I series needs the log Gamma(1 + v) table in LDS (orders
+// v <= 15, i.e. p <= 32, with kappa in the series region): every thread of
+// the workgroup loads it before lane 0 solves.
 __global__ __launch_bounds__(64) void k_vmf_kappa(const double *__restrict__ sumsq, int64_t n,
                                                   double p, double *__restrict__ out) {
+    __shared__ LgTab lt;
+    lgtab_load(&lt);
     if (threadIdx.x != 0)
         return;
     const double R = sqrt(*sumsq) / double(n);
@@ -780,8 +784,8 @@ __global__ __launch_bounds__(64) void k_vmf_kappa(const double *__restrict__ sum
     double prev = __builtin_inf();
     bool ok = (R > 0.0) && (R < 1.0) && (n > 0);
     for (; ok && it < 40; ++it) {
-        const double l0 = eval_full<double, KIND_I>(v, k, nullptr);
-        const double l1 = eval_full<double, KIND_I>(v + 1.0, k, nullptr);
+        const double l0 = eval_full<double, KIND_I>(v, k, &lt);
+        const double l1 = eval_full<double, KIND_I>(v + 1.0, k, &lt);
         const double A = exp(l1 - l0);
         const double kn = k - (A - R) / (1.0 - A * A - (p - 1.0) * A / k);
         const double d = fabs(kn - k);
@@ -1012,8 +1016,11 @@ int lbessel_classify(int kind, int precision, const void *v, const void *x, uint
     return launch_status();
 }
 
-int lbessel_eval_branch_f64(int kind, int branch, const double *v, const double *x, double *out,
-                            int64_t n, void *s) {
+}  // extern "C"
+
+template <typename T>
+static int run_branch(int kind, int branch, const T *v, const T *x, T *out, int64_t n,
+                      void *s) {
     if (n < 0 || (kind != 0 && kind != 1) || branch < 0 || branch > 2)
         return LBESSEL_EINVAL;
     if (n == 0)
@@ -1025,12 +1032,24 @@ int lbessel_eval_branch_f64(int kind, int branch, const double *v, const double 
         return LBESSEL_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(s);
     if (kind == 0)
-        hipLaunchKernelGGL(k_branch<KIND_I>, dim3(blocks), dim3(kThreads), 0, st, branch, v, x,
-                           out, n);
+        hipLaunchKernelGGL((k_branch<T, KIND_I>), dim3(blocks), dim3(kThreads), 0, st, branch, v,
+                           x, out, n);
     else
-        hipLaunchKernelGGL(k_branch<KIND_K>, dim3(blocks), dim3(kThreads), 0, st, branch, v, x,
-                           out, n);
+        hipLaunchKernelGGL((k_branch<T, KIND_K>), dim3(blocks), dim3(kThreads), 0, st, branch, v,
+                           x, out, n);
     return launch_status();
+}
+
+extern "C" {
+
+int lbessel_eval_branch_f64(int kind, int branch, const double *v, const double *x, double *out,
+                            int64_t n, void *s) {
+    return run_branch<double>(kind, branch, v, x, out, n, s);
+}
+
+int lbessel_eval_branch_f32(int kind, int branch, const float *v, const float *x, float *out,
+                            int64_t n, void *s) {
+    return run_branch<float>(kind, branch, v, x, out, n, s);
 }
 
 int lbessel_eval_ungrouped(int kind, int precision, const void *v, const void *x, void *out,

@@ -1,25 +1,28 @@
 """Per-branch VALU instruction counts for the roofline op model.
 
-Probe (GPU): every branch of log I and log K (f64) on 2^18 identical
-elements, one dispatch per probe point, so that an instruction-counter run
+Probe (GPU): every branch of log I and log K, binary64 and binary32, on 2^18
+identical elements, one dispatch per probe point, so that an
+instruction-counter run
 
     rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES -d <dir> -o opcount --output-format csv \
-        -- python -m paper_2409_08729_amd.opcount <dir>/opcount_points.json
+        -- python -m paper_2409_08729_amd.opcount <dir>/opcount_points.json f64,f32,quad
 
 reports the VALU instructions one evaluation issues with no divergence
 (per element = SQ_INSTS_VALU / SQ_WAVES: all 64 lanes of every wave run the
 same branch on the same input).  The probe writes the integrand node count of
-each K fallback point (lbessel_k_nodes) to the JSON file.
+each K fallback point (lbessel_k_nodes) to the JSON file.  The set "quad"
+probes the paper's own 600-node integral (the u_integral variant).
 
 Reduce (host):
 
     python -m paper_2409_08729_amd.opcount --reduce <counter_collection.csv> <points.json>
 
-writes paper_2409_08729_amd/opmodel.json.  The I series branch is probed at
-one point (its trip count varies mildly with (v, x)).  The K fallback's cost
-is setup + per_node x nodes, fitted by least squares over three points with
-different node counts (the fit residual is recorded); a launch's algorithmic
-ops then use each element's own node count.
+merges the probed sets into paper_2409_08729_amd/opmodel.json.  The I series
+branch is probed at one point (its trip count varies mildly with (v, x)).
+The K fallback's cost is setup + per_node x nodes, fitted by least squares
+over eight points with different node counts (the fit residuals are
+recorded); a launch's algorithmic ops then use each element's own node
+count.
 """
 from __future__ import annotations
 
@@ -28,72 +31,106 @@ import json
 import os
 import sys
 
-POINTS = [  # (kind, branch, v, x): well inside each branch's region; the Debye
-    # branch at one order per term-count tier (U_13, U_9, U_6, U_4)
-    ("I", 0, 3.0, 40.0), ("I", 1, 20.0, 10.0), ("I", 1, 40.0, 10.0), ("I", 1, 100.0, 10.0),
-    ("I", 1, 400.0, 10.0), ("I", 2, 3.0, 5.0),
-    ("K", 0, 3.0, 40.0), ("K", 1, 20.0, 10.0), ("K", 1, 40.0, 10.0), ("K", 1, 100.0, 10.0),
-    ("K", 1, 400.0, 10.0),
-    ("K", 2, 3.0, 5.0), ("K", 2, 0.5, 1e-4), ("K", 2, 12.0, 0.01),
-]
+# (precision, kind, branch, v, x): well inside each branch's region; the Debye
+# branch at one order per term-count tier (U_13, U_9, U_6, U_4); the K
+# fallback at points with different node counts.
+_FB_K64 = [(3.0, 5.0), (0.5, 1e-4), (12.0, 0.01), (1.0, 1.0), (6.0, 2.0), (0.1, 0.01),
+           (14.0, 10.0), (2.0, 15.0)]
+_FB_K32 = [(3.0, 5.0), (0.5, 1e-4), (8.0, 0.01), (1.0, 1.0), (6.0, 2.0), (0.1, 0.01),
+           (8.5, 5.0), (2.0, 6.5)]
+SETS = {
+    "f64": [(64, k, b, v, x) for k in ("I", "K") for b, v, x in
+            [(0, 3.0, 40.0), (1, 20.0, 10.0), (1, 40.0, 10.0), (1, 100.0, 10.0),
+             (1, 400.0, 10.0)]]
+           + [(64, "I", 2, 3.0, 5.0)] + [(64, "K", 2, v, x) for v, x in _FB_K64],
+    "f32": [(32, k, b, v, x) for k in ("I", "K") for b, v, x in
+            [(0, 3.0, 40.0), (1, 20.0, 10.0), (1, 40.0, 10.0), (1, 100.0, 10.0),
+             (1, 400.0, 10.0)]]
+           + [(32, "I", 2, 3.0, 5.0)] + [(32, "K", 2, v, x) for v, x in _FB_K32],
+    # the paper's integral (eq. log Kv integral) on its 600 nodes, trapezoid +
+    # Gregory weights: the u_integral variant on a uniform fallback array (one
+    # element per thread, no grouping); the per-element count is the same at
+    # every point of the fallback region (fixed node count)
+    "quad": [(64, "K", "u_integral", 3.0, 5.0), (64, "K", "u_integral", 0.5, 1e-4)],
+}
 U_TIER_NAMES = {20.0: "u13", 40.0: "u9", 100.0: "u6", 400.0: "u4"}
 NAMES = {0: "mu20", 2: "fallback"}
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "opmodel.json")
+PROBE_KERNELS = ("k_branch", "k_ungrouped")
 
 
-def probe(points_json: str | None, n: int = 1 << 18) -> None:
+def probe(points_json: str, sets: list[str], n: int = 1 << 18) -> None:
     import torch
     import paper_2409_08729_amd as lb
-    nodes = []
-    for kind, b, v0, x0 in POINTS:
-        v = torch.full((n,), v0, dtype=torch.float64, device="cuda:0")
-        x = torch.full((n,), x0, dtype=torch.float64, device="cuda:0")
-        lb.eval_branch(kind, b, v, x)
-        torch.cuda.synchronize()
-        c = int(lb.k_nodes(v[:1], x[:1]).item()) if (kind, b) == ("K", 2) else 0
-        nodes.append(c)
-        print(f"{kind} branch {b} at v={v0} x={x0}: {n} elements, {c} nodes", flush=True)
-    if points_json:
-        with open(points_json, "w") as f:
-            json.dump({"points": POINTS, "nodes": nodes}, f)
+    pts, nodes = [], []
+    for name in sets:
+        for prec, kind, b, v0, x0 in SETS[name]:
+            dt = torch.float64 if prec == 64 else torch.float32
+            v = torch.full((n,), v0, dtype=dt, device="cuda:0")
+            x = torch.full((n,), x0, dtype=dt, device="cuda:0")
+            if isinstance(b, str):
+                lb.eval_variant(kind, b, "naive", v, x)
+            else:
+                lb.eval_branch(kind, b, v, x)
+            torch.cuda.synchronize()
+            c = int(lb.k_nodes(v[:1], x[:1]).item()) if (kind, b) == ("K", 2) else 0
+            pts.append([name, prec, kind, b, v0, x0])
+            nodes.append(c)
+            print(f"{name}: {kind} branch {b} at v={v0} x={x0}: {n} elements, {c} nodes",
+                  flush=True)
+    with open(points_json, "w") as f:
+        json.dump({"points": pts, "nodes": nodes}, f)
 
 
 def reduce(path: str, points_json: str) -> dict:
+    """Merge the probed sets into opmodel.json (sets not probed are kept)."""
     import numpy as np
-    nodes = json.load(open(points_json))["nodes"]
+    meta = json.load(open(points_json))
+    pts, nodes = meta["points"], meta["nodes"]
     rows = list(csv.DictReader(open(path)))
     disp: dict = {}
     for r in rows:
         name = r.get("Kernel_Name", "")
-        if "k_branch" not in name:
+        if not any(k in name for k in PROBE_KERNELS):
             continue
         d = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0)
         disp.setdefault(d, {})[r["Counter_Name"]] = float(r["Counter_Value"])
     ids = sorted(disp)
-    if len(ids) != len(POINTS):
-        raise SystemExit(f"expected {len(POINTS)} k_branch dispatches, found {len(ids)}")
-    model = {"_doc": "VALU instructions per evaluation of each branch (binary64, no "
-                     "divergence): SQ_INSTS_VALU / SQ_WAVES of the probe dispatches of "
-                     "paper_2409_08729_amd/opcount.py.  K fallback: setup + per_node x "
-                     "nodes (least squares over the probe points).",
-             "I_f64": {}, "K_f64": {}}
-    fb = []
-    for d, (kind, b, v0, x0), c in zip(ids, POINTS, nodes):
+    if len(ids) != len(pts):
+        raise SystemExit(f"expected {len(pts)} probe dispatches, found {len(ids)}")
+    model = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    model["_doc"] = ("VALU instructions per evaluation of each branch (no divergence): "
+                     "SQ_INSTS_VALU / SQ_WAVES of the probe dispatches of "
+                     "paper_2409_08729_amd/opcount.py.  K fallback: setup + per_node x nodes "
+                     "(least squares over the probe points).  quad600_per_eval: the paper's "
+                     "600-node integral (u_integral variant), per fallback evaluation.")
+    fbs: dict = {}
+    for d, (name, prec, kind, b, v0, x0), c in zip(ids, pts, nodes):
         per = disp[d]["SQ_INSTS_VALU"] / disp[d]["SQ_WAVES"]
+        key = f"{kind}_f{prec}"
+        if name == "quad":
+            model.setdefault(key, {}).setdefault("quad600_probes", [])
+            model[key]["quad600_probes"] = [q for q in model[key]["quad600_probes"]
+                                            if (q["v"], q["x"]) != (v0, x0)]
+            model[key]["quad600_probes"].append({"v": v0, "x": x0, "valu": per})
+            model[key]["quad600_per_eval"] = float(np.mean(
+                [q["valu"] for q in model[key]["quad600_probes"]]))
+            continue
         if (kind, b) == ("K", 2):
-            fb.append((c, per, v0, x0))
+            fbs.setdefault(key, []).append((c, per, v0, x0))
         elif b == 1:
-            model[f"{kind}_f64"][U_TIER_NAMES[v0]] = per
+            model.setdefault(key, {})[U_TIER_NAMES[v0]] = per
         else:
-            model[f"{kind}_f64"][NAMES[b]] = per
-    A = np.array([[1.0, c] for c, _, _, _ in fb])
-    y = np.array([p for _, p, _, _ in fb])
-    (setup, per_node), *_ = np.linalg.lstsq(A, y, rcond=None)
-    model["K_f64"]["fallback_setup"] = float(setup)
-    model["K_f64"]["fallback_per_node"] = float(per_node)
-    model["K_f64"]["fallback_probes"] = [
-        {"v": v0, "x": x0, "nodes": c, "valu": p, "fit": float(setup + per_node * c)}
-        for c, p, v0, x0 in fb]
+            model.setdefault(key, {})[NAMES[b]] = per
+    for key, fb in fbs.items():
+        A = np.array([[1.0, c] for c, _, _, _ in fb])
+        y = np.array([p for _, p, _, _ in fb])
+        (setup, per_node), *_ = np.linalg.lstsq(A, y, rcond=None)
+        model[key]["fallback_setup"] = float(setup)
+        model[key]["fallback_per_node"] = float(per_node)
+        model[key]["fallback_probes"] = [
+            {"v": v0, "x": x0, "nodes": c, "valu": p, "fit": float(setup + per_node * c)}
+            for c, p, v0, x0 in fb]
     with open(OUT, "w") as f:
         json.dump(model, f, indent=1)
     return model
@@ -103,4 +140,5 @@ if __name__ == "__main__":
     if len(sys.argv) > 3 and sys.argv[1] == "--reduce":
         print(json.dumps(reduce(sys.argv[2], sys.argv[3]), indent=1))
     else:
-        probe(sys.argv[1] if len(sys.argv) > 1 else None)
+        # python -m paper_2409_08729_amd.opcount <points.json> [f64,f32,quad]
+        probe(sys.argv[1], (sys.argv[2] if len(sys.argv) > 2 else "f64,f32,quad").split(","))

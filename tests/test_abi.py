@@ -75,6 +75,8 @@ def test_diagnostic_argument_checks(lib):
     assert lib.lbessel_classify(2, 64, None, None, None, 0, None) == -1     # bad kind
     assert lib.lbessel_classify(0, 16, None, None, None, 0, None) == -1     # bad precision
     assert lib.lbessel_eval_branch_f64(0, 3, None, None, None, 0, None) == -1
+    assert lib.lbessel_eval_branch_f32(2, 0, None, None, None, 0, None) == -1
+    assert lib.lbessel_eval_branch_f32(0, 0, None, None, None, 0, None) == 0
     assert lib.lbessel_eval_ungrouped(1, 64, None, None, None, 0, None) == 0
 
 

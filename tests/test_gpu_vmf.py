@@ -77,3 +77,31 @@ def test_vmf_log_norm_gradient_vs_finite_difference(lb):
         kr = k.clone().requires_grad_(True)
         (gk,) = torch.autograd.grad(lb.VmfLogNorm.apply(kr, p).sum(), kr)
         assert torch.equal(gk, lb.vmf_log_norm_grad(k, p))
+
+
+@pytest.mark.parametrize("p", [2, 3, 10, 30])
+@pytest.mark.parametrize("a", [1.0, 3.0])
+def test_device_kappa_solve_low_concentration(lb, oracle, p, a):
+    """The device kappa solve where log I_{p/2-1}(kappa) takes the power series
+    (order p/2 - 1 <= 14 and kappa in ~1..20): rows a e_1 + N(0, I) give
+    mean resultant lengths from ~0.06 to ~0.94.  The solve must satisfy
+    A_p(kappa) = R (paper, eq. kappa estimates) with A_p from the oracle, and
+    kappa_0 must be R (p - R^2) / (1 - R^2)."""
+    import math
+    g = np.random.default_rng(1000 + p)
+    X = g.normal(size=(4000, p))
+    X[:, 0] += a
+    Xd = torch.from_numpy(X.astype(np.float32)).to("cuda:0")
+    k, R, k0, steps = lb.vmf_fit(Xd)
+    X64 = X.astype(np.float32).astype(np.float64)
+    U = X64 / np.linalg.norm(X64, axis=1, keepdims=True)
+    R_ref = float(np.linalg.norm(U.sum(0))) / X.shape[0]
+    assert abs(R - R_ref) <= 1e-12 * R_ref, (R, R_ref)
+    assert abs(k0 - R * (p - R * R) / (1 - R * R)) <= 1e-13 * k0
+    assert 0.5 < k < 25.0, k                    # inside the series region of the order
+    assert 1 <= steps <= 12, steps
+    v = np.array([p / 2 - 1, p / 2])
+    hi, lo = oracle.log_iv(v, np.array([k, k]))
+    a_ref = math.exp((hi[1] - hi[0]) + (lo[1] - lo[0]))
+    s = sum(max(abs(h), 1 + math.hypot(vv, k)) for h, vv in zip(hi, v))
+    assert abs(a_ref - R) <= TOL64 * s * a_ref + 1e-15, (p, k, a_ref, R)
