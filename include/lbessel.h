@@ -55,6 +55,7 @@ extern "C" {
 #define LBESSEL_EINVAL (-1)   /* NULL pointer with n > 0, n < 0, bad scalar   */
 #define LBESSEL_EHIP (-2)     /* the HIP runtime rejected a launch          */
 #define LBESSEL_ENODEV (-3)   /* no usable gfx950 device is current         */
+#define LBESSEL_ENOSPACE (-7) /* request needs more than the static buffer  */
 
 #define LBESSEL_ABI_VERSION 1
 
@@ -202,6 +203,28 @@ int lbessel_vmf_colsum_f32(const float *X, int64_t n, int64_t p, double *colsum,
 int64_t lbessel_vmf_fit_workspace(int64_t n, int64_t p);
 int lbessel_vmf_fit_f32(const float *X, int64_t n, int64_t p, double *result,
                         void *work, int64_t work_bytes, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fit as lbessel_vmf_fit_f32, bit for bit, with its workspace taken from a
+ * static device buffer of LBESSEL_VMF_FIT_STATIC_BYTES bytes instead of a
+ * caller argument.  The library holds one such buffer on each GPU it runs
+ * on, until the process ends; the first call on a device (with that device
+ * current) resolves the buffer's address, later calls allocate nothing.
+ * X and result are caller-owned device pointers as for lbessel_vmf_fit_f32.
+ * Returns LBESSEL_ENOSPACE when lbessel_vmf_fit_workspace(n, p) exceeds the
+ * buffer (24 MiB holds p = 32768 with n up to about 10^6 rows, and p = 2048
+ * with n up to about 2.6 * 10^6), LBESSEL_EINVAL for n < 1, p < 2 or a NULL
+ * pointer, LBESSEL_EHIP if the buffer's address cannot be resolved.
+ * Every call on one GPU uses that GPU's one buffer, which keeps the last
+ * call's contents (every word a call reads it writes first): calls that
+ * overlap in time on one GPU (several streams or host threads) race and
+ * must be serialised by the caller.
+ */
+#define LBESSEL_VMF_FIT_STATIC_BYTES (24LL << 20)
+int lbessel_vmf_fit_f32_noalloc(const float *X, int64_t n, int64_t p,
+                                double *result, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Segmented evaluation (many independent arrays in one launch)            */

@@ -13,6 +13,7 @@ vmf_log_norm(kappa, p), vmf_log_norm_grad  log C_p(kappa) and d/dkappa
 LogIv, LogKv, VmfLogNorm                   torch.autograd.Function wrappers
 vmf_colsum(X)                              column sums of L2-normalised rows
 vmf_fit(X)                                 device kappa solve (kappa, R, kappa_0, steps)
+vmf_fit_noalloc(X, result)                 the same into a caller tensor, no workspace
 eval_segments(kind, vs, xs)                many arrays in one segmented launch
 classify(kind, v, x), eval_branch(...),    diagnostics
 eval_ungrouped(kind, v, x)
@@ -72,6 +73,7 @@ def _load():
         "lbessel_eval_ungrouped": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_vmf_colsum_f32": [vp, i64, i64, vp, vp, vp, i64, vp],
         "lbessel_vmf_fit_f32": [vp, i64, i64, vp, vp, i64, vp],
+        "lbessel_vmf_fit_f32_noalloc": [vp, i64, i64, vp, vp],
         "lbessel_eval_segments": [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, i64, vp],
         "lbessel_abi_version": [],
         "lbessel_status_string": [ctypes.c_int],
@@ -256,6 +258,24 @@ def vmf_fit(X: torch.Tensor):
                                        work.numel(), _stream(X)), "lbessel_vmf_fit_f32")
     k, R, k0, steps = res.cpu().tolist()
     return k, R, k0, int(steps)
+
+
+def vmf_fit_noalloc(X: torch.Tensor, result: torch.Tensor) -> torch.Tensor:
+    """vmf_fit into result (4 float64 on X's device: kappa, R, kappa_0,
+    Newton steps), with the workspace in the library's static device buffer:
+    nothing is allocated.  Calls that overlap on one GPU race."""
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2:
+        raise LbesselError("X must be a 2-D float32 tensor on a GPU")
+    if not X.is_contiguous():
+        raise LbesselError("X must be contiguous (a copy would allocate)")
+    if (not isinstance(result, torch.Tensor) or result.device != X.device
+            or result.dtype != torch.float64 or result.numel() < 4 or not result.is_contiguous()):
+        raise LbesselError("result must be 4 contiguous float64 on X's device")
+    n, p = X.shape
+    with torch.cuda.device(X.device):
+        _check(_load().lbessel_vmf_fit_f32_noalloc(X.data_ptr(), n, p, result.data_ptr(),
+                                                   _stream(X)), "lbessel_vmf_fit_f32_noalloc")
+    return result
 
 
 class Segment(ctypes.Structure):

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include <hipcub/hipcub.hpp>
 
 #include "lbessel.h"
@@ -816,6 +818,32 @@ inline int launch_status() {
     return (hipGetLastError() == hipSuccess) ? LBESSEL_OK : LBESSEL_EHIP;
 }
 
+// Workspace of lbessel_vmf_fit_f32_noalloc: one copy per GPU, at its own
+// address on each.  In host code the name stands for no device address: host
+// code uses only the per-device pointer that hipGetSymbolAddress returns.
+static __device__ __align__(256) double scratch[LBESSEL_VMF_FIT_STATIC_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of scratch per device id
+
+// Device address of scratch on the current device, resolved on the first
+// call per device and cached.
+int static_scratch_on_current_device(void **ptr) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return LBESSEL_ENODEV;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return LBESSEL_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return LBESSEL_OK;
+}
+
 inline bool grid_ok(int64_t n, int per_block, uint32_t *blocks) {
     const int64_t b = (n + per_block - 1) / per_block;
     if (b > int64_t(0x7fffffff))
@@ -1157,6 +1185,25 @@ int64_t lbessel_vmf_fit_workspace(int64_t n, int64_t p) {
     return (w < 0) ? w : w + (p + 1) * int64_t(sizeof(double));
 }
 
+int lbessel_vmf_fit_f32_noalloc(const float *X, int64_t n, int64_t p, double *result, void *s) {
+    constexpr int64_t cap = LBESSEL_VMF_FIT_STATIC_BYTES;
+    if (n < 1 || p < 2 || X == nullptr || result == nullptr)
+        return LBESSEL_EINVAL;
+    // the workspace holds at least p + n doubles: bound both before sizing it
+    if (p > cap / int64_t(sizeof(double)) || n > cap / int64_t(sizeof(double)))
+        return LBESSEL_ENOSPACE;
+    const int64_t need = lbessel_vmf_fit_workspace(n, p);
+    if (need < 0)
+        return LBESSEL_EINVAL;
+    if (need > cap)
+        return LBESSEL_ENOSPACE;
+    void *work = nullptr;
+    const int rc = static_scratch_on_current_device(&work);
+    if (rc != LBESSEL_OK)
+        return rc;
+    return lbessel_vmf_fit_f32(X, n, p, result, work, cap, s);
+}
+
 int lbessel_eval_segments(int kind, int precision, const lbessel_segment_t *segs, int nseg,
                           int64_t tiles, void *s) {
     if ((kind != 0 && kind != 1) || (precision != 64 && precision != 32) || nseg < 0 ||
@@ -1296,6 +1343,7 @@ const char *lbessel_status_string(int status) {
     case LBESSEL_EINVAL: return "invalid argument";
     case LBESSEL_EHIP: return "HIP launch failure";
     case LBESSEL_ENODEV: return "no usable device";
+    case LBESSEL_ENOSPACE: return "request larger than the static buffer";
     case LBESSEL_ETOOBIG: return "request larger than the server arena";
     case LBESSEL_ETIMEOUT: return "timed out";
     case LBESSEL_ESTOPPED: return "server stopped";

@@ -102,6 +102,33 @@ def test_segment_and_fit_argument_checks(lib):
     assert lib.lbessel_vmf_fit_f32(None, 10, 8, None, None, 0, None) == -1
 
 
+def test_noalloc_fit_size_checks(lib):
+    """The no-allocation fit rejects NULL pointers and sizes beyond its static
+    buffer on the host, before touching a device."""
+    fn = lib.lbessel_vmf_fit_f32_noalloc
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                   ctypes.c_void_p]
+    fn.restype = ctypes.c_int
+    fake = ctypes.c_void_p(1 << 20)    # never dereferenced: every call below fails first
+    assert fn(None, 10, 8, fake, None) == -1
+    assert fn(fake, 10, 8, None, None) == -1
+    assert fn(fake, 0, 8, fake, None) == -1                 # n < 1
+    assert fn(fake, 10, 1, fake, None) == -1                # p < 2
+    assert fn(fake, 2_000_000, 32768, fake, None) == -7     # 26.2 MB > 24 MiB
+    assert fn(fake, 3_000_000, 2048, fake, None) == -7
+    assert fn(fake, 10, 1 << 40, fake, None) == -7          # p alone exceeds the buffer
+    assert fn(fake, 1 << 40, 8, fake, None) == -7
+    assert lib.lbessel_status_string(-7) == b"request larger than the static buffer"
+    lib.lbessel_vmf_fit_workspace.restype = ctypes.c_int64
+    lib.lbessel_vmf_fit_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64]
+    # the documented limits: p = 32768 to about 1.0e6 rows, p = 2048 to 2.6e6
+    cap = 24 << 20
+    assert lib.lbessel_vmf_fit_workspace(1_015_807, 32768) <= cap
+    assert lib.lbessel_vmf_fit_workspace(1_015_808, 32768) > cap
+    assert lib.lbessel_vmf_fit_workspace(2_619_391, 2048) <= cap
+    assert lib.lbessel_vmf_fit_workspace(2_619_392, 2048) > cap
+
+
 def test_server_needs_a_device():
     import torch
     from paper_2409_08729_amd import serve
