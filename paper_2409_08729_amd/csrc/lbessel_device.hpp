@@ -60,6 +60,13 @@ __device__ __forceinline__ double lexp(double a) { return fm::exp64(a); }
 __device__ __forceinline__ double llog(double a) { return fm::log64(a); }
 __device__ __forceinline__ float lexp(float a) { return expf(a); }
 __device__ __forceinline__ float llog(float a) { return logf(a); }
+// log(1 + a), a >= 0, to ~1 ulp relative also for a near 0: the log of the
+// rounded sum u = 1 + a plus the rounding error of that sum over u
+__device__ __forceinline__ double llog1p(double a) { return fm::log1p64(a); }
+__device__ __forceinline__ float llog1p(float a) {
+    const float u = 1.0f + a;
+    return fmaf(a - (u - 1.0f), fm::rcp_hw(u), logf(u));
+}
 // exp of an argument known to satisfy |a| < 1e9
 __device__ __forceinline__ double lexp_b(double a) { return fm::exp64_bounded(a); }
 // reciprocal: Newton-refined hardware estimate in binary64 (<= 1 ulp); the
@@ -440,9 +447,12 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     // d_k = k (k + v), so a_k = a_{k-1} q d_{k+1} / (d_k d_{k+1}) and
     // a_{k+1} = a_{k-1} q^2 / (d_k d_{k+1}).  The stop test runs on the second
     // term of a pair, so at most one term more than a per-term test is summed.
+    // The sum is kept without its leading 1 (sum of a_k / a_0 over k >= 1)
+    // and enters through log1p: where I_v(x) is close to (x/2)^v / Gamma(v+1)
+    // (small x) its log stays accurate relative to the small correction.
     const T q2 = q * q;
     T term = T(1);
-    T sum = T(1);
+    T sum = T(0);
     for (int k = 1; k < 200; k += 2) {
         const T f0 = T(k), f1 = T(k + 1);
         const T d0 = f0 * (f0 + v);
@@ -452,7 +462,7 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
         term = term * q2 * r;
         sum = sum + t0;
         sum = sum + term;
-        if (d1 > T(2) * q && term < Cst<T>::series_eps * sum)
+        if (d1 > T(2) * q && term < fma(Cst<T>::series_eps, sum, Cst<T>::series_eps))
             break;
     }
     T lg;
@@ -461,7 +471,7 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     else
         lg = lgamma(v + T(1));
     // log(x/2) as log x - log 2: x/2 can underflow for subnormal x
-    return v * (llog(x) - Cst<T>::ln2) - lg + llog(sum);
+    return v * (llog(x) - Cst<T>::ln2) - lg + llog1p(sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -920,7 +930,7 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
 // With v fixed at 0 or 1 every expansion reduces to polynomials with constant
 // coefficients (tables generated in exact or 100-digit arithmetic):
 //   x > x1 (the Hankel region of both orders): br_mu, as on the general path;
-//   I:  log I_v = v log(x/2) + log sum_k q^k/(k!(k+v)!),  q = x^2/4
+//   I:  log I_v = v log(x/2) + log1p(sum_{k>=1} q^k/(k!(k+v)!)),  q = x^2/4
 //       (DLMF 10.25.2; 48 terms cover x <= 21.5);
 //   K, 2 < x <= x1: log K_v = g_v(1/x) - x - 1/2 log(2x/pi), g_v a degree-20
 //       Chebyshev expansion in s = 1/x on [1/17.5, 1/2] (Clenshaw);
@@ -962,8 +972,10 @@ __device__ __forceinline__ T order01(T x) {
     const T q = T(0.25) * x * x;
     const LB_CONST_AS T *ser = opaque_const<T>(Tab01<T>::iser()) + V * tables::kI01Terms;
     if (KIND == KIND_I) {
-        const T s = horner<T, tables::kI01Terms>(ser, q);
-        return (V == 0) ? llog(s) : lx2 + llog(s);
+        // sum = 1 + q h(q): log1p of q h keeps log I_0 ~ x^2/4 accurate
+        // relative to itself for small x
+        const T qh = q * horner<T, tables::kI01Terms - 1>(ser + 1, q);
+        return (V == 0) ? llog1p(qh) : lx2 + llog1p(qh);
     }
     if (x > T(2)) {
         // Clenshaw on u = (2s - (sa + sb)) / (sb - sa), s = 1/x

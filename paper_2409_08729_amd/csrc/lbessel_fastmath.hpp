@@ -155,6 +155,16 @@ __host__ __device__ __forceinline__ double log64(double a) {
     return fma(de, kLn2Hi, -((hfsq - fma(s, hfsq + r, de * kLn2Lo)) - f));
 }
 
+// log(1 + t) for finite t >= 0.  u = 1 + t rounded; then
+// log(1 + t) = log(u) + log(1 + d/u) with d = t - (u - 1) the rounding error
+// of the sum (u - 1 and d are exact), and log(1 + d/u) = d/u to within
+// (d/u)^2 <= 2^-106.  Relative error ~1 ulp for every t, where log64(1 + t)
+// has an absolute error of ~2^-53 (large relative error for t near 0).
+__host__ __device__ __forceinline__ double log1p64(double t) {
+    const double u = 1.0 + t;
+    return fma(t - (u - 1.0), rcp_nr(u), log64(u));
+}
+
 // binary32 hardware approximations (v_exp_f32, v_log_f32, v_rcp_f32,
 // v_rsq_f32, v_sqrt_f32; about one binary32 ulp) for quantities that only
 // steer an algorithm (a Newton start and iterate, a step size, a shift,

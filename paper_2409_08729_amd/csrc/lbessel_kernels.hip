@@ -172,9 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_ungrouped(Args<T> a) {
 // ---------------------------------------------------------------------------
 // Grouped kernel
 // ---------------------------------------------------------------------------
-template <int NV> struct TileCfg {
+template <int NV, int NTH = kThreads> struct TileCfg {
     static constexpr int ept = 4;                        // elements per thread
-    static constexpr int tile = kThreads * ept;          // elements per tile
+    static constexpr int tile = NTH * ept;               // elements per tile
     static constexpr int slots = ept * NV;               // evaluations per thread
 };
 
@@ -202,8 +202,29 @@ template <int KIND, int OP, int VAR> struct Classes {
     static constexpr int u0 = 1;          // first Debye class
     static constexpr int f0 = 1 + ub;     // first fallback class
     static constexpr int n = 1 + ub + fb;
-    static constexpr int bits = (n > 3) ? 4 : 2;
+    static constexpr int bits = (n > 15) ? 5 : (n > 3) ? 4 : 2;
     static constexpr int none = (1 << bits) - 1;
+};
+
+// Workgroup size of a grouped kernel.  The one-order K kernels run 512
+// threads on 2048-element tiles: their fallback elements (~40% of a mixed
+// launch) differ ~10x in cost, and the longer each class-sorted list, the
+// fewer of its 64-lane chunks straddle two cost classes (2^26-pair stress
+// grid: 3.15 -> 2.95 ms against 1024-element tiles; 4096-element tiles gain
+// little more there and lose on launches of one class, whose 16-wave
+// workgroups wait at the tile barrier with little else to overlap).  Their
+// LDS grows with the tile (16 bytes of staging per element): four
+// workgroups per CU, 32 waves.  The other kernels keep 256 threads.
+#ifndef LBESSEL_K_THREADS
+#define LBESSEL_K_THREADS 512
+#endif
+template <int KIND, int OP, int VAR> struct GroupShape {
+    static constexpr int threads =
+        (KIND == KIND_K && OpTraits<OP>::nv == 1 && (VAR == VAR_DEFAULT || VAR == VAR_PAPER_REGIMES))
+            ? LBESSEL_K_THREADS
+            : kThreads;
+    // LDS-bound at 4 (or 2) workgroups per CU: 8 waves per SIMD (<= 64 VGPRs)
+    static constexpr int waves_per_eu = (threads > kThreads) ? 8 : 1;
 };
 
 // One-order operations of K, and of I in binary32 (STAGE): the tile's (order,
@@ -215,16 +236,18 @@ template <int KIND, int OP, int VAR> struct Classes {
 // 8 workgroups per CU to 6, which costs more than the L2 re-reads.  The
 // two-order operations finish a tile quickly enough that the step-4 re-reads
 // hit L2.
-template <typename T, int NV, int NC, bool STAGE> struct Smem {
-    T sv[STAGE ? TileCfg<NV>::tile : 1];                 // order, then result
-    T sx[STAGE ? TileCfg<NV>::tile : 1];                 // argument
-    uint16_t list[TileCfg<NV>::tile * NV];               // evaluation ids, class-sorted
-    uint16_t cnt[NC][TileCfg<NV>::slots][kWaves];        // counts, then offsets
+template <typename T, int NV, int NC, bool STAGE, int NTH> struct Smem {
+    using Cfg = TileCfg<NV, NTH>;
+    static constexpr int NW = NTH / 64;
+    T sv[STAGE ? Cfg::tile : 1];                         // order, then result
+    T sx[STAGE ? Cfg::tile : 1];                         // argument
+    uint16_t list[Cfg::tile * NV];                       // evaluation ids, class-sorted
+    uint16_t cnt[NC][Cfg::slots][NW];                    // counts, then offsets
     int start[NC];                                       // first list position per class
     int n_fb, n_fb_u, n_all;                             // list segment ends
-    uint32_t wmask[kWaves];                              // classes present, per wave
+    uint32_t wmask[NW];                                  // classes present, per wave
     int chunk;                                           // next chunk to evaluate
-    T res[(NV == 2) ? TileCfg<NV>::tile * 2 : 1];        // log-values of both orders
+    T res[(NV == 2) ? Cfg::tile * 2 : 1];                // log-values of both orders
 };
 
 __device__ __forceinline__ int rank_below(uint64_t m) {
@@ -232,22 +255,25 @@ __device__ __forceinline__ int rank_below(uint64_t m) {
                                      __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
 }
 
-// One tile (workgroup-wide: every thread of the workgroup must call it).
-template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
+// One tile of NTH threads (workgroup-wide: every thread of the workgroup must
+// call it).
+template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT, int NTH = kThreads>
 __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     static_assert(VAR != VAR_SEVEN, "the grouped kernel sorts three branches");
     constexpr int NV = OpTraits<OP>::nv;
-    constexpr int EPT = TileCfg<NV>::ept;
-    constexpr int TILE = TileCfg<NV>::tile;
-    constexpr int SLOTS = TileCfg<NV>::slots;
+    constexpr int EPT = TileCfg<NV, NTH>::ept;
+    constexpr int TILE = TileCfg<NV, NTH>::tile;
+    constexpr int SLOTS = TileCfg<NV, NTH>::slots;
+    constexpr int NW = NTH / 64;
     using C = Classes<KIND, OP, VAR>;
     constexpr int NC = C::n;
     constexpr int BITS = C::bits;
     constexpr uint32_t MASK = (1u << BITS) - 1;
     static_assert(SLOTS * BITS <= 32, "class codes of one thread fit 32 bits");
-    static_assert(NC * SLOTS <= 64, "one lane clears each (class, slot) count");
+    static_assert(NC < 32, "class masks fit 32 bits");
+    static_assert(TILE * NV <= 65536, "evaluation ids fit 16 bits");
     constexpr bool STAGE = (NV == 1) && (KIND == KIND_K || sizeof(T) == 4);
-    __shared__ Smem<T, NV, NC, STAGE> sm;
+    __shared__ Smem<T, NV, NC, STAGE, NTH> sm;
 
     // the fallback's tables, loaded below only if the tile has fallback work
     FbTab<KIND, T> *kt = fb_tab_storage<KIND, T>();
@@ -268,7 +294,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     T vr[EPT], xr[EPT];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
-        const int e = r * kThreads + tid;
+        const int e = r * NTH + tid;
         const int64_t i = base + e;
         int b0 = C::none, b1 = C::none;
         vr[r] = T(0);
@@ -329,8 +355,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     for (int off = 32; off > 0; off >>= 1)
         present |= uint32_t(__shfl_xor(int(present), off));
     present = __builtin_amdgcn_readfirstlane(present);
-    if (lane < NC * SLOTS)
-        sm.cnt[lane / SLOTS][lane % SLOTS][wave] = 0;
+    for (int c = lane; c < NC * SLOTS; c += 64)
+        sm.cnt[c / SLOTS][c % SLOTS][wave] = 0;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int b = (code >> (BITS * s)) & MASK;
@@ -352,7 +378,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     // element is the same either way.
     uint32_t tile_mask = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w)
+    for (int w = 0; w < NW; ++w)
         tile_mask |= sm.wmask[w];
     if (NV == 1 && (tile_mask & (tile_mask - 1)) == 0) {   // workgroup-uniform
         if (tile_mask == 0)
@@ -365,7 +391,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
         for (int r = 0; r < EPT; ++r) {
             if (done & (1u << r))
                 continue;
-            const int e = r * kThreads + tid;
+            const int e = r * NTH + tid;
             const T v = STAGE ? sm.sv[e] : KEEP ? vr[r] : order_of<T, KIND, OP>(a, base + e);
             const T x = STAGE ? sm.sx[e] : KEEP ? xr[r] : a.x[base + e];
             const T y = eval_branch<T, KIND, VAR>(b, v, x, kt);
@@ -378,7 +404,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
         const int br = tid;
         int run = 0;
         for (int s = 0; s < SLOTS; ++s)
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 const int c = sm.cnt[br][s][w];
                 sm.cnt[br][s][w] = run;
                 run += c;
@@ -424,7 +450,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             if (b == br) {
                 const int pos = sm.start[br] + sm.cnt[br][s][wave] + rank_below(m);
                 const int r = s / NV, sub = s - (s / NV) * NV;
-                sm.list[pos] = uint16_t((r * kThreads + tid) * NV + sub);
+                sm.list[pos] = uint16_t((r * NTH + tid) * NV + sub);
             }
         }
     }
@@ -468,7 +494,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
         for (int r = 0; r < EPT; ++r) {
             if (done & (1u << r))
                 continue;
-            const int e = r * kThreads + tid;
+            const int e = r * NTH + tid;
             const T y = sm.sv[e];
             a.out[base + e] = combine<T, KIND, OP>(vs, sm.sx[e], T(1), a.p, y, y);
         }
@@ -482,7 +508,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
         for (int r = 0; r < EPT; ++r) {
             if (done & (1u << r))
                 continue;
-            const int e = r * kThreads + tid;
+            const int e = r * NTH + tid;
             const int64_t i = base + e;
             const T v = order_of<T, KIND, OP>(a, i);
             const T x = a.x[i];
@@ -493,8 +519,22 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
 }
 
 template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
-__global__ __launch_bounds__(kThreads) void k_grouped(Args<T> a) {
-    grouped_tile<T, KIND, OP, VAR>(a, blockIdx.x);
+__global__ __launch_bounds__((GroupShape<KIND, OP, VAR>::threads))
+__attribute__((amdgpu_waves_per_eu(GroupShape<KIND, OP, VAR>::waves_per_eu)))
+void k_grouped(Args<T> a) {
+    grouped_tile<T, KIND, OP, VAR, GroupShape<KIND, OP, VAR>::threads>(a, blockIdx.x);
+}
+
+// Launch of k_grouped over a.n elements with its workgroup size and tile.
+template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
+int launch_grouped(const Args<T> &a, hipStream_t st) {
+    constexpr int nth = GroupShape<KIND, OP, VAR>::threads;
+    constexpr int tile = TileCfg<OpTraits<OP>::nv, nth>::tile;
+    const int64_t b = (a.n + tile - 1) / tile;
+    if (b > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    hipLaunchKernelGGL((k_grouped<T, KIND, OP, VAR>), dim3(uint32_t(b)), dim3(nth), 0, st, a);
+    return (hipGetLastError() == hipSuccess) ? LBESSEL_OK : LBESSEL_EHIP;
 }
 
 // ---------------------------------------------------------------------------
@@ -863,13 +903,8 @@ int run_grouped(const T *v, const T *x, const T *g, T *out, int64_t n, T vs, T p
     }
     if (n == 0)
         return LBESSEL_OK;
-    uint32_t blocks;
-    if (!grid_ok(n, TileCfg<OpTraits<OP>::nv>::tile, &blocks))
-        return LBESSEL_EINVAL;
     Args<T> a{v, x, g, out, n, vs, p};
-    hipLaunchKernelGGL((k_grouped<T, KIND, OP>), dim3(blocks), dim3(kThreads), 0,
-                       static_cast<hipStream_t>(s), a);
-    return launch_status();
+    return launch_grouped<T, KIND, OP>(a, static_cast<hipStream_t>(s));
 }
 
 template <typename T, int KIND>
@@ -971,11 +1006,8 @@ static int run_order(T v, const T *x, T *out, int64_t n, hipStream_t st) {
                                out, n);
         return launch_status();
     }
-    if (!grid_ok(n, TileCfg<1>::tile, &blocks))
-        return LBESSEL_EINVAL;
     Args<T> a{nullptr, x, nullptr, out, n, v, T(0)};
-    hipLaunchKernelGGL((k_grouped<T, KIND, OP_LOG>), dim3(blocks), dim3(kThreads), 0, st, a);
-    return launch_status();
+    return launch_grouped<T, KIND, OP_LOG>(a, st);
 }
 
 extern "C" {
@@ -1268,11 +1300,7 @@ static int run_variant(int layout, const double *v, const double *x, double *out
     if (layout == LBESSEL_LAYOUT_GROUPED) {
         if (VAR == VAR_SEVEN)
             return LBESSEL_EINVAL;
-        if (!grid_ok(n, TileCfg<1>::tile, &blocks))
-            return LBESSEL_EINVAL;
-        hipLaunchKernelGGL((k_grouped<double, KIND, OP_LOG, (VAR == VAR_SEVEN ? 0 : VAR)>),
-                           dim3(blocks), dim3(kThreads), 0, st, a);
-        return launch_status();
+        return launch_grouped<double, KIND, OP_LOG, (VAR == VAR_SEVEN ? 0 : VAR)>(a, st);
     }
     if (!grid_ok(n, kThreads, &blocks))
         return LBESSEL_EINVAL;
