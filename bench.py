@@ -432,27 +432,35 @@ def paper_tables_bench(lb, torch):
             "note": "paper times are the RTX 2080 Ti means of its Tables 6 and 7 (context)"}
 
 
-def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
+def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9), resident="host"):
     """Open-loop Poisson request stream through the native server: uneven
-    evaluation requests (host arrays, 1 .. 4M pairs, I/K, f64/f32) and vMF
-    fits (device features, p in {2048, 8192, 32768}, N in [1e3, 5e4]).
-    Saturation = all requests offered at once; then offered loads at the
-    given fractions of the batched server's saturation rate.  Latency =
-    completion - scheduled arrival."""
+    evaluation requests (1 .. 4M pairs, I/K, f64/f32) with their arrays in
+    pinned host memory (resident="host": copied in and out by the server) or
+    on the GPU (resident="device": no copies), and vMF fits (device
+    features, p in {2048, 8192, 32768}, N in [1e3, 5e4]).  Saturation = all
+    requests offered at once; then offered loads at the given fractions of
+    the batched server's saturation rate.  Latency = completion - scheduled
+    arrival."""
     from paper_2409_08729_amd import serve, workloads as wl
     reqs, gaps = wl.serving_requests(count)
     v, x = wl.serving_pool()
-    pools = {64: (torch.from_numpy(v).pin_memory(), torch.from_numpy(x).pin_memory()),
-             32: (torch.from_numpy(v.astype(np.float32)).pin_memory(),
-                  torch.from_numpy(x.astype(np.float32)).pin_memory())}
+    dev = resident == "device"
+
+    def place(a):
+        t = torch.from_numpy(a)
+        return t.to("cuda:0") if dev else t.pin_memory()
+    pools = {64: (place(v), place(x)),
+             32: (place(v.astype(np.float32)), place(x.astype(np.float32)))}
     feats = {p: wl.vmf_features(wl.SERVE_VMF_ROWS[1], p, seed=p, device="cuda:0")
              for p in wl.SERVE_VMF_DIMS}
     tot = {64: 0, 32: 0}
     for r in reqs:
         if r["type"] == "eval":
             tot[r["precision"]] += r["n"]
-    outbuf = {64: torch.empty(tot[64], dtype=torch.float64, pin_memory=True),
-              32: torch.empty(tot[32], dtype=torch.float32, pin_memory=True)}
+    outbuf = {64: torch.empty(tot[64], dtype=torch.float64, pin_memory=not dev,
+                              device="cuda:0" if dev else "cpu"),
+              32: torch.empty(tot[32], dtype=torch.float32, pin_memory=not dev,
+                              device="cuda:0" if dev else "cpu")}
     results = torch.empty((count, 4), dtype=torch.float64, pin_memory=True)
     base, at = [], {64: 0, 32: 0}
     for i, r in enumerate(reqs):
@@ -461,7 +469,8 @@ def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
             o, n = r["offset"], r["n"]
             a = at[r["precision"]]
             at[r["precision"]] += n
-            base.append({"type": "eval", "kind": r["kind"], "v": pv[o:o + n], "x": px[o:o + n],
+            base.append({"type": "eval_device" if dev else "eval", "kind": r["kind"],
+                         "v": pv[o:o + n], "x": px[o:o + n],
                          "out": outbuf[r["precision"]][a:a + n]})
         else:
             base.append({"type": "vmf", "X": feats[r["p"]][: r["N"]], "result": results[i]})
@@ -488,7 +497,7 @@ def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
     run("plain", zeros)
     sat = {}
     for label, _, _ in modes:
-        log(f"serving: saturation, {label}")
+        log(f"serving ({resident}): saturation, {label}")
         sat[label] = run(label, zeros)
     unit_t = np.cumsum(gaps)
     sweep = []
@@ -496,21 +505,99 @@ def serving_bench(torch, count=1024, loads=(0.25, 0.5, 0.75, 0.9)):
         qps = f * sat["batched"]["requests_per_s"]
         row = {"load": f, "offered_requests_per_s": qps}
         for label, _, _ in modes:
-            log(f"serving: load {f:.2f} ({qps:.0f} req/s), {label}")
+            log(f"serving ({resident}): load {f:.2f} ({qps:.0f} req/s), {label}")
             row[label] = run(label, unit_t / qps)
         sweep.append(row)
     n_vmf = sum(r["type"] == "vmf" for r in reqs)
     return {"requests": count, "eval_requests": count - n_vmf, "vmf_requests": n_vmf,
             "eval_pairs": pairs,
+            "resident": resident,
             "mix": "eval: n log-uniform [1, 4M], kind I/K and f64/f32 equally likely, "
-                   "log10 v ~ U[-3,4] (1/256 of v = 0), log10 x ~ U[-3,4], host pinned "
-                   "in/out; vMF (1/8 of requests): p in {2048, 8192, 32768}, N log-uniform "
+                   "log10 v ~ U[-3,4] (1/256 of v = 0), log10 x ~ U[-3,4], "
+                   + ("in/out on the device" if dev else "host pinned in/out")
+                   + "; vMF (1/8 of requests): p in {2048, 8192, 32768}, N log-uniform "
                    "[1e3, 5e4], features on the device",
             "modes": {"batched": "FIFO memory admission, continuous batching into segmented "
                                  "launches of up to 2^18 pairs, 8 batches in flight",
                       "plain": "same queue, one request at a time, one launch per request",
                       "plain_8streams": "one launch per request, 8 requests in flight"},
             "saturation": sat, "sweep": sweep}
+
+
+def graph_bench(lb, torch, nseg=16, reps=400):
+    """Launch cost of one small serving batch (nseg device-resident requests
+    of log-uniform size in [1, 4096], log K f64, one segmented launch with
+    the table in the kernel arguments): issued directly through the C-ABI,
+    or captured once in a HIP graph and replayed.  Reports host time per
+    submission and GPU time per batch for both (the saving a graph-replayed
+    batch path could bring), and checks every replay against the eager
+    result."""
+    import ctypes
+    from paper_2409_08729_amd import workloads as wl
+    g = np.random.default_rng(41)
+    v, x = wl.serving_pool(1 << 16, seed=42)
+    dv = torch.from_numpy(v).to("cuda:0")
+    dx = torch.from_numpy(x).to("cuda:0")
+    lib = lb.lib()
+    table = (lb.Segment * nseg)()
+    outs, tiles, at = [], 0, 0
+    for k in range(nseg):
+        n = int(np.exp(g.uniform(0.0, np.log(4096.0))))
+        o = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        table[k] = lb.Segment(dv[at:].data_ptr(), dx[at:].data_ptr(), o.data_ptr(), n, tiles)
+        tiles += lib.lbessel_segment_tiles(n)
+        outs.append((o, at, n))
+        at += n
+    addr = ctypes.addressof(table)
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        rc = lib.lbessel_eval_segments_inline(1, 64, addr, nseg, tiles, stream.cuda_stream)
+        assert rc == 0
+
+    launch()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o, _, _ in outs]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        host = (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        return host * 1e6, e0.elapsed_time(e1) * 1e3 / reps
+
+    direct_host, direct_gpu = timed(launch)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for o, _, _ in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            rc = lib.lbessel_eval_segments_inline(1, 64, addr, nseg, tiles, side.cuda_stream)
+            assert rc == 0
+    torch.cuda.synchronize()
+    same = True
+    for _ in range(3):   # replays with eager work and synchronisation between them
+        for o, _, _ in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        same = same and all(torch.equal(a.view(torch.int64), o.view(torch.int64))
+                            for a, (o, _, _) in zip(eager, outs))
+    graph_host, graph_gpu = timed(graph.replay)
+    return {"batch": f"{nseg} log K f64 requests, {at} pairs, {tiles} tiles, one launch",
+            "direct_host_us": direct_host, "direct_gpu_us_per_batch": direct_gpu,
+            "graph_host_us": graph_host, "graph_gpu_us_per_batch": graph_gpu,
+            "graph_replays_equal_eager": same}
 
 
 def main():
@@ -634,19 +721,32 @@ def main():
     if not args.no_ablation:
         ablations = ablation_bench(lb, torch, sets)
     paper_k = None
-    if ablations is not None and "quad600_per_eval" in om.get("K_f64", {}):
-        # the paper's own K fallback (eq. log Kv integral, 600 nodes; u_integral
-        # variant, Debye at 13 terms everywhere) on the stress grid
+    if "quad600_per_eval" in om.get("K_f64", {}):
+        # the paper's own K fallback (eq. log Kv integral, 600 nodes, Debye at
+        # 13 terms everywhere): lbessel_log_kv_integral_f64 on the stress grid
         c = mix[(js, "K")]
         ck = om["K_f64"]
         ops = (c["mu20"] * ck["mu20"] + (c["u13"] + c["u9"] + c["u6"] + c["u4"]) * ck["u13"]
                + c["fallback"] * ck["quad600_per_eval"])
-        ms = ablations["results"]["u_integral/grouped"]["K"][f"{stress}_ms"]
-        paper_k = roofline_block(ops, ms, "k_grouped<double, K, log, u_integral> "
-                                 "(lbessel_eval_variant u_integral, grouped)",
+        _, sv, sx = sets[js]
+        o = lb.log_kv_integral(sv, sx)
+        ts = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lb.log_kv_integral(sv, sx)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        del o
+        paper_k = roofline_block(ops, float(np.median(ts)),
+                                 "k_grouped<double, K, log, u_integral> "
+                                 "(lbessel_log_kv_integral_f64)",
                                  f"{stress}: {sets[js][1].numel()} pairs", sets[js][1].numel(),
                                  24, "log_kv_f64_stress_u_integral")
         paper_k["quad600_per_eval"] = ck["quad600_per_eval"]
+        paper_k["speedup_of_default_path"] = paper_k["launch_ms"] / kern[f"K:{stress}"]["ms"]
     order01, paper_tables = None, None
     if not args.no_tables:
         log("orders 0/1 and the paper's runtime tables")
@@ -656,6 +756,10 @@ def main():
     vmf_res = None
     if not args.no_vmf:
         vmf_res = vmf_bench(lb, torch)
+    launch_cost = None
+    if not args.no_serving:
+        log("launch cost: direct vs graph replay")
+        launch_cost = graph_bench(lb, torch)
 
     cpu, errors = None, None
     if not args.no_cpu_baseline:
@@ -669,7 +773,8 @@ def main():
     if not args.no_serving:
         del outs
         torch.cuda.empty_cache()
-        serving = serving_bench(torch)
+        serving = {"host": serving_bench(torch, resident="host"),
+                   "device": serving_bench(torch, resident="device")}
 
     workload = ("log I_v and log K_v, f64: 20M pairs per order v=2^0..2^10 with x~U[1,100) "
                 "plus the 2^26-pair stress grid (log10 v~U[-3,4], log10 x~U[-4,4])")
@@ -680,6 +785,7 @@ def main():
         "max_err_on_oracle_sample": errors, "ms_I_per_step": i_ms, "ms_K_per_step": k_ms,
         "f32": f32, "paper_k": paper_k, "grouping_ablation": ablation, "ablations": ablations,
         "order01": order01, "paper_tables": paper_tables, "vmf": vmf_res, "serving": serving,
+        "launch_cost": launch_cost,
         "kernels": kern,
     }
     if args.detail:
@@ -725,10 +831,20 @@ def main():
                 k: f32["roofline"][k] for k in keep if k in f32["roofline"]},
             "errors": errsum(f32.get("errors"))},
         "paper_k_u_integral": None if paper_k is None else {
-            k: paper_k[k] for k in ("launch_ms", "frac", "valu_busy", "active_lanes")
+            k: paper_k[k] for k in ("launch_ms", "frac", "valu_busy", "active_lanes",
+                                    "speedup_of_default_path")
             if k in paper_k},
-        "serving_saturation_req_s": None if serving is None else {
-            k: v["requests_per_s"] for k, v in serving["saturation"].items()},
+        "serving": None if serving is None else {
+            res: {"saturation_req_s": {k: v["requests_per_s"]
+                                       for k, v in serving[res]["saturation"].items()},
+                  "p50_p99_ms_at_0.9": {k: [serving[res]["sweep"][-1][k]["p50_ms"],
+                                            serving[res]["sweep"][-1][k]["p99_ms"]]
+                                        for k in ("batched", "plain_8streams")}}
+            for res in serving},
+        "launch_cost_us": None if launch_cost is None else {
+            k: launch_cost[k] for k in ("direct_host_us", "direct_gpu_us_per_batch",
+                                        "graph_host_us", "graph_gpu_us_per_batch",
+                                        "graph_replays_equal_eager")},
     }
     print(json.dumps(line), flush=True)
 

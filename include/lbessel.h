@@ -13,7 +13,7 @@
  * integral, 600 nodes); this library's K fallback instead applies the
  * trapezoid rule to K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF
  * 10.32.9) for x >= 1e-10, and the leading terms of DLMF 10.27.4 below; the
- * paper's integral stays available through lbessel_eval_variant.  All
+ * paper's integral stays available as lbessel_log_kv_integral_f64.  All
  * intermediate quantities stay on a log scale, so results are finite
  * wherever log I_v(x) and log K_v(x) are.
  *
@@ -89,6 +89,24 @@ int lbessel_log_kv_f64(const double *v, const double *x, double *out,
                        int64_t n, void *stream);
 int lbessel_log_kv_f32(const float *v, const float *x, float *out,
                        int64_t n, void *stream);
+
+/*
+ * out[i] = log K_{v[i]}(x[i]) by the paper's own small-argument method for K
+ * (Sec. "Theory", eq. (log Kv integral) with n = 8, the composite rule after
+ * it and the maxima of "Finding heuristics for maximums"): the integral of
+ * g + h over u in (0, 1] on the paper's 600 nodes u_k = k/600, each term
+ * exponentiated relative to the heuristic maximum of its part.  Weights:
+ * trapezoid with an order-8 Gregory end correction (the paper's composite
+ * Simpson rule misses the binary64 target by orders of magnitude; it stays
+ * available as LBESSEL_VAR_SIMPSON).  The Hankel and Debye branches and the
+ * special values are those of lbessel_log_kv_f64.  Same results as
+ * lbessel_eval_variant(1, LBESSEL_VAR_U_INTEGRAL, LBESSEL_LAYOUT_GROUPED, ..),
+ * within the same accuracy bar as lbessel_log_kv_f64; it runs 600 integrand
+ * evaluations per fallback element where lbessel_log_kv_f64 runs 10-150.
+ * Binary64 only.
+ */
+int lbessel_log_kv_integral_f64(const double *v, const double *x, double *out,
+                                int64_t n, void *stream);
 
 /*
  * One order for the whole array: out[i] = log I_v(x[i]) / log K_v(x[i]).
@@ -243,6 +261,19 @@ typedef struct lbessel_segment {
     int64_t n;
     int64_t tile0;
 } lbessel_segment_t;
+
+/*
+ * The same launch with the descriptor table in HOST memory, at most
+ * LBESSEL_SEG_INLINE_MAX entries: the table is copied into the kernel's
+ * arguments when the call enqueues the launch, so no device table and no
+ * copy on the stream are needed (the serving runtime's small batches); segs
+ * may be reused as soon as the call returns.  Results as for
+ * lbessel_eval_segments.  nseg > LBESSEL_SEG_INLINE_MAX -> LBESSEL_EINVAL.
+ */
+#define LBESSEL_SEG_INLINE_MAX 32
+int lbessel_eval_segments_inline(int kind, int precision,
+                                 const lbessel_segment_t *segs, int nseg,
+                                 int64_t tiles, void *stream);
 
 /* Workgroup tiles covering n elements in a segmented launch (n >= 0). */
 int64_t lbessel_segment_tiles(int64_t n);

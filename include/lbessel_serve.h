@@ -3,11 +3,15 @@
  * (include/lbessel.h) for a stream of uneven requests, such as the Poisson
  * request streams of a metric-learning or inference service.
  *
- * Two request types:
+ * Request types:
  *   - evaluation: n pairs (v, x) in HOST memory -> n log-values into host
  *     memory; kind 0 = log I_v(x), 1 = log K_v(x); precision 64 or 32.
  *     Pinned host memory (hipHostMalloc) lets the copies overlap compute;
  *     pageable memory works but serialises the server on each copy.
+ *   - device-resident evaluation: the same with v, x and out in DEVICE
+ *     memory (arrays a model on the same GPU produced or consumes): no
+ *     copies, no arena data; the batch's segmented launch reads and writes
+ *     the caller's arrays directly.
  *   - vMF fit: an n x p float32 feature matrix in DEVICE memory (typically
  *     the output of a model on the same GPU) -> the maximum-likelihood
  *     concentration, computed on the device (lbessel_vmf_fit_f32), into 4
@@ -24,7 +28,9 @@
  *      order up to the batch caps (a large evaluation request or a vMF fit
  *      goes out alone): its host inputs are copied in, all evaluation
  *      requests of one (kind, precision) run as ONE segmented launch
- *      (lbessel_eval_segments), vMF requests run their column-sum and
+ *      (lbessel_eval_segments; up to LBESSEL_SEG_INLINE_MAX requests per
+ *      launch with the segment table in the kernel arguments,
+ *      lbessel_eval_segments_inline), vMF requests run their column-sum and
  *      Newton kernels, and the outputs are copied back.  Requests that
  *      arrive while batches are on the GPU are admitted as memory frees up
  *      and go out with the next batch; up to `streams` batches overlap
@@ -137,6 +143,17 @@ int lbessel_server_submit_eval(lbessel_server_t *s, int kind, int precision, con
                                const void *x, void *out, int64_t n, int64_t *ticket);
 
 /*
+ * Queue a device-resident evaluation request: v, x, out DEVICE arrays of n
+ * elements (double for precision 64, float for 32), complete before the call
+ * (the server's streams do not wait on the caller's); out receives the
+ * log-values.  The request holds no arena memory.  Errors as for
+ * lbessel_server_submit_eval.
+ */
+int lbessel_server_submit_eval_device(lbessel_server_t *s, int kind, int precision,
+                                      const void *v, const void *x, void *out, int64_t n,
+                                      int64_t *ticket);
+
+/*
  * Queue a vMF fit: X device, row-major float32, n rows of p columns
  * (1 <= n <= 2^31 - 1, p >= 2), complete before the call (the server's
  * streams do not wait on the caller's); result: host, 4 doubles as in
@@ -170,9 +187,11 @@ int lbessel_server_destroy(lbessel_server_t *s);
  * call starts (items sorted by t_arrival), from the calling thread, then
  * wait for all of them.  info[i] receives each record, with t_arrival the
  * scheduled time, so t_done - t_arrival is the latency a client sees.
- * type 0 = evaluation (kind, precision, v, x, out, n), 1 = vMF fit
- * (X, n, p, result).  Returns LBESSEL_OK, or the first error (submission
- * errors stop the replay; requests already queued are still waited for).
+ * type 0 = evaluation (kind, precision, v, x, out, n) with host arrays,
+ * 1 = vMF fit (X, n, p, result), 2 = evaluation with device arrays
+ * (lbessel_server_submit_eval_device); any other type is LBESSEL_EINVAL.
+ * Returns LBESSEL_OK, or the first error (submission errors stop the replay;
+ * requests already queued are still waited for).
  */
 typedef struct lbessel_replay_item {
     double t_arrival;

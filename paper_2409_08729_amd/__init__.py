@@ -7,6 +7,7 @@ HIP kernels; there is no CPU path.  If the library is not built, or a tensor
 is not on a GPU, the call raises.
 
 log_iv(v, x), log_kv(v, x)                 log I_v(x), log K_v(x)
+log_kv_integral(v, x)                      log K_v(x) with the paper's 600-node integral
 log_iv_order(v, x), log_kv_order(v, x)     one scalar order (fast path for v = 0, 1)
 log_iv_grad_x(v, x, g), log_kv_grad_x(..)  g * d/dx log I_v(x), log K_v(x)
 vmf_log_norm(kappa, p), vmf_log_norm_grad  log C_p(kappa) and d/dkappa
@@ -53,6 +54,7 @@ def _load():
         "lbessel_log_iv_f32": [vp, vp, vp, i64, vp],
         "lbessel_log_kv_f64": [vp, vp, vp, i64, vp],
         "lbessel_log_kv_f32": [vp, vp, vp, i64, vp],
+        "lbessel_log_kv_integral_f64": [vp, vp, vp, i64, vp],
         "lbessel_log_iv_grad_x_f64": [vp, vp, vp, vp, i64, vp],
         "lbessel_log_iv_grad_x_f32": [vp, vp, vp, vp, i64, vp],
         "lbessel_log_kv_grad_x_f64": [vp, vp, vp, vp, i64, vp],
@@ -75,6 +77,8 @@ def _load():
         "lbessel_vmf_fit_f32": [vp, i64, i64, vp, vp, i64, vp],
         "lbessel_vmf_fit_f32_noalloc": [vp, i64, i64, vp, vp],
         "lbessel_eval_segments": [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, i64, vp],
+        "lbessel_eval_segments_inline": [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, i64,
+                                         vp],
         "lbessel_abi_version": [],
         "lbessel_status_string": [ctypes.c_int],
     }
@@ -147,6 +151,20 @@ def log_iv(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
 def log_kv(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     """log K_v(x), elementwise, float64 or float32."""
     return _unary("lbessel_log_kv", v, x)
+
+
+def log_kv_integral(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """log K_v(x), float64, with the paper's own 600-node integral as the
+    small-argument branch (lbessel_log_kv_integral_f64)."""
+    v, x = _prep(v, x)
+    if x.dtype != torch.float64:
+        raise LbesselError("log_kv_integral takes float64 tensors")
+    out = torch.empty_like(x)
+    with torch.cuda.device(x.device):
+        _check(_load().lbessel_log_kv_integral_f64(v.data_ptr(), x.data_ptr(), out.data_ptr(),
+                                                   x.numel(), _stream(x)),
+               "lbessel_log_kv_integral_f64")
+    return out
 
 
 def _order(name: str, v: float, x: torch.Tensor) -> torch.Tensor:
@@ -284,9 +302,12 @@ class Segment(ctypes.Structure):
                 ("n", ctypes.c_int64), ("tile0", ctypes.c_int64)]
 
 
-def eval_segments(kind: str, vs, xs):
+def eval_segments(kind: str, vs, xs, inline: bool = False):
     """log I or log K of several (v, x) array pairs in ONE segmented launch;
-    returns the list of outputs (each equals log_iv/log_kv of that pair)."""
+    returns the list of outputs (each equals log_iv/log_kv of that pair).
+    inline: pass the segment table in the kernel arguments
+    (lbessel_eval_segments_inline, at most 32 non-empty pairs) instead of a
+    device copy."""
     if len(vs) != len(xs):
         raise LbesselError("vs and xs must have the same length")
     pairs = [_prep(v, x) for v, x in zip(vs, xs)]
@@ -306,9 +327,16 @@ def eval_segments(kind: str, vs, xs):
         table[k] = Segment(v.data_ptr(), x.data_ptr(), o.data_ptr(), x.numel(), tiles)
         tiles += lib.lbessel_segment_tiles(x.numel())
         k += 1
+    prec = 64 if dt == torch.float64 else 32
+    if inline:
+        with torch.cuda.device(dev):
+            _check(lib.lbessel_eval_segments_inline(KIND[kind], prec, ctypes.addressof(table), k,
+                                                    tiles, _stream(pairs[0][1])),
+                   "lbessel_eval_segments_inline")
+            torch.cuda.current_stream(dev).synchronize()
+        return outs
     host = torch.frombuffer(bytearray(bytes(table)), dtype=torch.uint8)
     dseg = host.to(dev)
-    prec = 64 if dt == torch.float64 else 32
     with torch.cuda.device(dev):
         _check(lib.lbessel_eval_segments(KIND[kind], prec, dseg.data_ptr(), k, tiles,
                                          _stream(dseg)), "lbessel_eval_segments")

@@ -584,9 +584,10 @@ __global__ __launch_bounds__(kThreads) void k_sorted_eval(const uint8_t *__restr
 // up to the next segment's tile0; each tile is the same grouped_tile as in
 // the single-array kernel, so every result equals the single-array one.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND>
-__global__ __launch_bounds__(kThreads) void k_grouped_seg(
-    const lbessel_segment_t *__restrict__ segs, int nseg) {
+// Tile blockIdx.x of a segmented launch over segs[0 .. nseg): segs is a
+// device table or the kernel-argument copy of k_grouped_seg_inline.
+template <typename T, int KIND, typename Segs>
+__device__ __forceinline__ void seg_tile(const Segs &segs, int nseg) {
     const int64_t t = blockIdx.x;
     // largest s with segs[s].tile0 <= t (uniform across the workgroup)
     int lo = 0, hi = nseg - 1;
@@ -603,6 +604,23 @@ __global__ __launch_bounds__(kThreads) void k_grouped_seg(
     Args<T> a{static_cast<const T *>(sg.v), static_cast<const T *>(sg.x), nullptr,
               static_cast<T *>(sg.out), sg.n, T(0), T(0)};
     grouped_tile<T, KIND, OP_LOG>(a, t - sg.tile0);
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_grouped_seg(
+    const lbessel_segment_t *__restrict__ segs, int nseg) {
+    seg_tile<T, KIND>(segs, nseg);
+}
+
+// The segment table passed by value in the kernel arguments (no device copy).
+struct SegPack {
+    lbessel_segment_t s[LBESSEL_SEG_INLINE_MAX];
+    __device__ const lbessel_segment_t &operator[](int i) const { return s[i]; }
+};
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_grouped_seg_inline(SegPack pack, int nseg) {
+    seg_tile<T, KIND>(pack, nseg);
 }
 
 // ---------------------------------------------------------------------------
@@ -944,6 +962,16 @@ int lbessel_log_kv_f32(const float *v, const float *x, float *out, int64_t n, vo
     return run_grouped<float, KIND_K, OP_LOG>(v, x, nullptr, out, n, 0.f, 0.f, s);
 }
 
+int lbessel_log_kv_integral_f64(const double *v, const double *x, double *out, int64_t n,
+                                void *s) {
+    if (n < 0 || (n > 0 && (v == nullptr || x == nullptr || out == nullptr)))
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    Args<double> a{v, x, nullptr, out, n, 0.0, 0.0};
+    return launch_grouped<double, KIND_K, OP_LOG, VAR_U_INTEGRAL>(a, static_cast<hipStream_t>(s));
+}
+
 int lbessel_log_iv_grad_x_f64(const double *v, const double *x, const double *g, double *gx,
                               int64_t n, void *s) {
     return run_grouped<double, KIND_I, OP_GRAD>(v, x, g, gx, n, 0.0, 0.0, s);
@@ -1258,6 +1286,38 @@ int lbessel_eval_segments(int kind, int precision, const lbessel_segment_t *segs
             hipLaunchKernelGGL((k_grouped_seg<float, KIND_I>), grid, block, 0, st, sg, nseg);
         else
             hipLaunchKernelGGL((k_grouped_seg<float, KIND_K>), grid, block, 0, st, sg, nseg);
+    }
+    return launch_status();
+}
+
+int lbessel_eval_segments_inline(int kind, int precision, const lbessel_segment_t *segs,
+                                 int nseg, int64_t tiles, void *s) {
+    if ((kind != 0 && kind != 1) || (precision != 64 && precision != 32) || nseg < 0 ||
+        nseg > LBESSEL_SEG_INLINE_MAX || tiles < 0 || tiles > int64_t(0x7fffffff))
+        return LBESSEL_EINVAL;
+    if (nseg == 0 || tiles == 0)
+        return LBESSEL_OK;
+    if (segs == nullptr)
+        return LBESSEL_EINVAL;
+    SegPack pack{};
+    for (int k = 0; k < nseg; ++k)
+        pack.s[k] = segs[k];
+    hipStream_t st = static_cast<hipStream_t>(s);
+    const dim3 grid{uint32_t(tiles)}, block{kThreads};
+    if (precision == 64) {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_grouped_seg_inline<double, KIND_I>), grid, block, 0, st, pack,
+                               nseg);
+        else
+            hipLaunchKernelGGL((k_grouped_seg_inline<double, KIND_K>), grid, block, 0, st, pack,
+                               nseg);
+    } else {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_grouped_seg_inline<float, KIND_I>), grid, block, 0, st, pack,
+                               nseg);
+        else
+            hipLaunchKernelGGL((k_grouped_seg_inline<float, KIND_K>), grid, block, 0, st, pack,
+                               nseg);
     }
     return launch_status();
 }

@@ -74,7 +74,7 @@ class Arena {
     int64_t total_, used_ = 0, peak_ = 0;
 };
 
-enum ReqType { REQ_EVAL = 0, REQ_VMF = 1 };
+enum ReqType { REQ_EVAL = 0, REQ_VMF = 1, REQ_EVAL_DEVICE = 2 };
 
 struct Request {
     int64_t id = 0;
@@ -87,6 +87,7 @@ struct Request {
     int64_t p = 0;
     double *hres = nullptr;
     int64_t off = -1;
+    bool dev = false;   // evaluation arrays in device memory: no copies, no arena data
     lbessel_request_info_t info{};
 
     int group() const { return (precision == 64 ? 0 : 2) + kind; }
@@ -143,7 +144,7 @@ struct lbessel_server {
 
 int64_t lbessel_server::bytes_of(const Request &r) const {
     if (r.type == REQ_EVAL)
-        return std::max<int64_t>(kAlign, 3 * r.span());   // v, x, out
+        return r.dev ? kAlign : std::max<int64_t>(kAlign, 3 * r.span());   // v, x, out
     const int64_t w = lbessel_vmf_fit_workspace(r.n, r.p);
     return (w < 0) ? -1 : kVmfResult + align_up(w);
 }
@@ -183,11 +184,11 @@ int lbessel_server::enqueue(Slot &sl, int64_t *launches) {
         for (Request *r : sl.reqs) {
             if (r->type != REQ_EVAL || r->group() != g)
                 continue;
-            char *dv = arena_dev + r->off;
-            char *dx = dv + r->span();
-            char *dout = dx + r->span();
+            char *dv = r->dev ? (char *)r->hv : arena_dev + r->off;
+            char *dx = r->dev ? (char *)r->hx : dv + r->span();
+            char *dout = r->dev ? (char *)r->hout : dx + r->span();
             const int64_t nb = r->n * r->elem();
-            if (nb > 0) {
+            if (nb > 0 && !r->dev) {
                 hip(hipMemcpyAsync(dv, r->hv, nb, hipMemcpyHostToDevice, st));
                 hip(hipMemcpyAsync(dx, r->hx, nb, hipMemcpyHostToDevice, st));
             }
@@ -212,16 +213,21 @@ int lbessel_server::enqueue(Slot &sl, int64_t *launches) {
             }
         }
         if (!plain && tiles > 0) {
-            lbessel_segment_t *ds = sl.dseg + int64_t(g) * cap;
-            hip(hipMemcpyAsync(ds, hs, count * sizeof(lbessel_segment_t), hipMemcpyHostToDevice,
-                               st));
-            keep(lbessel_eval_segments(kind, prec, ds, count, tiles, st));
+            if (count <= LBESSEL_SEG_INLINE_MAX) {
+                // small batch: the table rides in the kernel arguments
+                keep(lbessel_eval_segments_inline(kind, prec, hs, count, tiles, st));
+            } else {
+                lbessel_segment_t *ds = sl.dseg + int64_t(g) * cap;
+                hip(hipMemcpyAsync(ds, hs, count * sizeof(lbessel_segment_t),
+                                   hipMemcpyHostToDevice, st));
+                keep(lbessel_eval_segments(kind, prec, ds, count, tiles, st));
+            }
             ++*launches;
         }
         for (Request *r : sl.reqs) {
             if (r->type != REQ_EVAL || r->group() != g)
                 continue;
-            if (r->n > 0) {
+            if (r->n > 0 && !r->dev) {
                 const char *dout = arena_dev + r->off + 2 * r->span();
                 hip(hipMemcpyAsync(r->hout, dout, r->n * r->elem(), hipMemcpyDeviceToHost, st));
             }
@@ -461,6 +467,24 @@ int lbessel_server_submit_eval(lbessel_server_t *s, int kind, int precision, con
     return s->submit(std::move(r), ticket);
 }
 
+int lbessel_server_submit_eval_device(lbessel_server_t *s, int kind, int precision,
+                                      const void *v, const void *x, void *out, int64_t n,
+                                      int64_t *ticket) {
+    if (s == nullptr || (kind != 0 && kind != 1) || (precision != 64 && precision != 32) ||
+        n < 0 || (n > 0 && (v == nullptr || x == nullptr || out == nullptr)))
+        return LBESSEL_EINVAL;
+    auto r = std::make_unique<Request>();
+    r->type = REQ_EVAL;
+    r->dev = true;
+    r->kind = kind;
+    r->precision = precision;
+    r->hv = v;
+    r->hx = x;
+    r->hout = out;
+    r->n = n;
+    return s->submit(std::move(r), ticket);
+}
+
 int lbessel_server_submit_vmf(lbessel_server_t *s, const float *X, int64_t n, int64_t p,
                               double *result, int64_t *ticket) {
     if (s == nullptr || X == nullptr || result == nullptr || n < 1 || n > int64_t(0x7fffffff) ||
@@ -557,10 +581,17 @@ int lbessel_server_replay(lbessel_server_t *s, const lbessel_replay_item_t *item
             else
                 std::this_thread::yield();
         }
-        const int e = (it.type == REQ_EVAL)
-                          ? lbessel_server_submit_eval(s, it.kind, it.precision, it.v, it.x,
-                                                       it.out, it.n, &tickets[i])
-                          : lbessel_server_submit_vmf(s, it.X, it.n, it.p, it.result, &tickets[i]);
+        int e;
+        if (it.type == REQ_EVAL)
+            e = lbessel_server_submit_eval(s, it.kind, it.precision, it.v, it.x, it.out, it.n,
+                                           &tickets[i]);
+        else if (it.type == REQ_EVAL_DEVICE)
+            e = lbessel_server_submit_eval_device(s, it.kind, it.precision, it.v, it.x, it.out,
+                                                  it.n, &tickets[i]);
+        else if (it.type == REQ_VMF)
+            e = lbessel_server_submit_vmf(s, it.X, it.n, it.p, it.result, &tickets[i]);
+        else
+            e = LBESSEL_EINVAL;
         if (e != LBESSEL_OK) {
             rc = e;
             break;

@@ -2,8 +2,9 @@
 
 Argument marshalling only: the queue, admission, batching and every kernel
 live in liblbessel.so.  Evaluation requests take pinned host tensors
-(``torch.empty(..., pin_memory=True)``) for inputs and outputs; vMF fit
-requests take a float32 feature matrix on the GPU.
+(``torch.empty(..., pin_memory=True)``) for inputs and outputs, or GPU
+tensors (submit_eval_device: no copies); vMF fit requests take a float32
+feature matrix on the GPU.
 
     srv = Server(mode="batched")
     t = srv.submit_eval("K", v_host, x_host, out_host)
@@ -68,6 +69,8 @@ def _lib():
         "lbessel_server_default_config": ([ctypes.POINTER(Config)], None),
         "lbessel_server_create": ([ctypes.POINTER(Config), ctypes.POINTER(vp)], ci),
         "lbessel_server_submit_eval": ([vp, ci, ci, vp, vp, vp, i64, ctypes.POINTER(i64)], ci),
+        "lbessel_server_submit_eval_device": ([vp, ci, ci, vp, vp, vp, i64,
+                                               ctypes.POINTER(i64)], ci),
         "lbessel_server_submit_vmf": ([vp, vp, i64, i64, vp, ctypes.POINTER(i64)], ci),
         "lbessel_server_wait": ([vp, i64, cd, ctypes.POINTER(RequestInfo)], ci),
         "lbessel_server_clock": ([vp], cd),
@@ -87,6 +90,14 @@ def _lib():
 def _err(status: int, what: str) -> LbesselError:
     msg = _load().lbessel_status_string(status).decode()
     return LbesselError(f"{what} failed: {msg} ({status})")
+
+
+def _device(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise LbesselError(f"{name} must be a contiguous GPU tensor")
+    if t.dtype not in (torch.float64, torch.float32):
+        raise LbesselError(f"{name}: float64 or float32 only")
+    return t
 
 
 def _host(t: torch.Tensor, name: str) -> torch.Tensor:
@@ -136,6 +147,24 @@ class Server:
         self._keep[t.value] = (v, x, out)
         return t.value
 
+    def submit_eval_device(self, kind: str, v: torch.Tensor, x: torch.Tensor,
+                           out: torch.Tensor) -> int:
+        """Device-resident evaluation request: v, x, out GPU tensors (the
+        inputs complete on the current stream before this returns)."""
+        v, x, out = _device(v, "v"), _device(x, "x"), _device(out, "out")
+        if not (v.dtype == x.dtype == out.dtype) or not (v.numel() == x.numel() == out.numel()):
+            raise LbesselError("v, x, out must share dtype and size")
+        prec = 64 if v.dtype == torch.float64 else 32
+        torch.cuda.current_stream(v.device).synchronize()   # inputs complete before submit
+        t = ctypes.c_int64()
+        rc = _lib().lbessel_server_submit_eval_device(self._h, KIND[kind], prec, v.data_ptr(),
+                                                      x.data_ptr(), out.data_ptr(), v.numel(),
+                                                      ctypes.byref(t))
+        if rc != 0:
+            raise _err(rc, "lbessel_server_submit_eval_device")
+        self._keep[t.value] = (v, x, out)
+        return t.value
+
     def submit_vmf(self, X: torch.Tensor, result: torch.Tensor) -> int:
         if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
             raise LbesselError("X must be a contiguous 2-D float32 tensor on the GPU")
@@ -162,15 +191,18 @@ class Server:
 
     def replay(self, items, timeout: float = 600.0):
         """items: list of dicts, sorted by 't' (arrival, seconds from the start):
-        {'t', 'type': 'eval', 'kind', 'v', 'x', 'out'} or
+        {'t', 'type': 'eval', 'kind', 'v', 'x', 'out'} (host tensors),
+        {'t', 'type': 'eval_device', 'kind', 'v', 'x', 'out'} (GPU tensors) or
         {'t', 'type': 'vmf', 'X', 'result'}.  Returns one info dict per item."""
         arr = (ReplayItem * len(items))()
         for i, it in enumerate(items):
             r = arr[i]
             r.t_arrival = float(it["t"])
-            if it["type"] == "eval":
-                v, x, out = _host(it["v"], "v"), _host(it["x"], "x"), _host(it["out"], "out")
-                r.type, r.kind = 0, KIND[it["kind"]]
+            if it["type"] in ("eval", "eval_device"):
+                conv = _host if it["type"] == "eval" else _device
+                v, x, out = conv(it["v"], "v"), conv(it["x"], "x"), conv(it["out"], "out")
+                r.type = 0 if it["type"] == "eval" else 2
+                r.kind = KIND[it["kind"]]
                 r.precision = 64 if v.dtype == torch.float64 else 32
                 r.v, r.x, r.out, r.n = v.data_ptr(), x.data_ptr(), out.data_ptr(), v.numel()
             else:

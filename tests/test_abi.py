@@ -47,7 +47,8 @@ def test_version_and_status(lib):
 
 
 @pytest.mark.parametrize("name", ["lbessel_log_iv_f64", "lbessel_log_iv_f32",
-                                  "lbessel_log_kv_f64", "lbessel_log_kv_f32"])
+                                  "lbessel_log_kv_f64", "lbessel_log_kv_f32",
+                                  "lbessel_log_kv_integral_f64"])
 def test_forward_argument_checks(lib, name):
     fn = getattr(lib, name)
     assert fn(None, None, None, 0, None) == 0          # n = 0: nothing to do
@@ -95,6 +96,11 @@ def test_segment_and_fit_argument_checks(lib):
     assert lib.lbessel_eval_segments(0, 64, None, 0, 0, None) == 0         # empty batch
     assert lib.lbessel_eval_segments(2, 64, None, 0, 0, None) == -1        # bad kind
     assert lib.lbessel_eval_segments(0, 64, None, 3, 5, None) == -1        # NULL table
+    fake = ctypes.c_void_p(1 << 20)     # never read: every call below fails first
+    assert lib.lbessel_eval_segments_inline(0, 64, fake, 33, 5, None) == -1  # > 32 entries
+    assert lib.lbessel_eval_segments_inline(0, 16, fake, 3, 5, None) == -1
+    assert lib.lbessel_eval_segments_inline(0, 64, None, 3, 5, None) == -1
+    assert lib.lbessel_eval_segments_inline(0, 64, None, 0, 0, None) == 0
     lib.lbessel_vmf_fit_f32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p]

@@ -24,9 +24,10 @@ def lb():
 SIZES = [0, 1, 63, 2047, 2048, 2049, 7000, 100_003]
 
 
+@pytest.mark.parametrize("inline", [False, True])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("kind", ["I", "K"])
-def test_segmented_launch_equals_single_array(lb, kind, dtype):
+def test_segmented_launch_equals_single_array(lb, kind, dtype, inline):
     from paper_2409_08729_amd import workloads as wl
     v, x = wl.serving_pool(sum(SIZES), seed=11)
     vs, xs, at = [], [], 0
@@ -34,7 +35,7 @@ def test_segmented_launch_equals_single_array(lb, kind, dtype):
         vs.append(torch.from_numpy(v[at:at + n]).to("cuda:0", dtype))
         xs.append(torch.from_numpy(x[at:at + n]).to("cuda:0", dtype))
         at += n
-    outs = lb.eval_segments(kind, vs, xs)
+    outs = lb.eval_segments(kind, vs, xs, inline=inline)
     f = lb.log_iv if kind == "I" else lb.log_kv
     for vv, xx, o in zip(vs, xs, outs):
         ref = f(vv, xx)
@@ -239,3 +240,53 @@ def test_large_requests_and_fits_go_out_alone(lb):
         if r["type"] == "vmf" or r["n"] >= solo:
             assert len(members[i["batch"]]) == 1, (r["type"], r.get("n"))
     assert any(len(m) > 1 for m in members.values())
+
+
+def test_device_resident_requests_same_alone_and_in_mix(lb):
+    """Evaluation requests whose arrays live on the GPU (no copies): the same
+    bits alone, in a batched mix (batches of more and of fewer than 32
+    requests: device and inline segment tables) and in plain mode, and the
+    same as the single-array entry point."""
+    from paper_2409_08729_amd import serve, workloads as wl
+    g = np.random.default_rng(31)
+    v, x = wl.serving_pool(1 << 20, seed=32)
+    reqs = []
+    for i in range(80):
+        n = int(np.exp(g.uniform(0.0, np.log(20_000))))
+        at = int(g.integers(0, v.size - n))
+        dt = torch.float64 if i % 3 else torch.float32
+        reqs.append({"type": "eval_device", "kind": "IK"[i % 2],
+                     "v": torch.from_numpy(v[at:at + n]).to("cuda:0", dt),
+                     "x": torch.from_numpy(x[at:at + n]).to("cuda:0", dt)})
+    reqs.append({"type": "eval_device", "kind": "K",
+                 "v": torch.empty(0, dtype=torch.float64, device="cuda:0"),
+                 "x": torch.empty(0, dtype=torch.float64, device="cuda:0")})
+
+    def fresh():
+        for r in reqs:
+            r["out"] = torch.full_like(r["v"], float("nan"))
+        torch.cuda.synchronize()
+
+    fresh()
+    with serve.Server("batched", arena_bytes=1 << 20) as srv:
+        for r in reqs:
+            t = srv.submit_eval_device(r["kind"], r["v"], r["x"], r["out"])
+            assert srv.wait(t, timeout=60)["status"] == 0
+    alone = [r["out"].clone() for r in reqs]
+    for r, a in zip(reqs, alone):
+        f = lb.log_iv if r["kind"] == "I" else lb.log_kv
+        assert _same_bits(a, f(r["v"], r["x"])), (r["kind"], r["v"].dtype, r["v"].numel())
+    for mode, cap in (("batched", 64), ("batched", 8), ("plain", 64)):
+        fresh()
+        items = [{"t": 0.0, "type": "eval_device", "kind": r["kind"], "v": r["v"], "x": r["x"],
+                  "out": r["out"]} for r in reqs]
+        # the arena holds no request data: a tiny one admits everything
+        with serve.Server(mode, arena_bytes=1 << 16, streams=4,
+                          max_batch_requests=cap) as srv:
+            infos = srv.replay(items, timeout=120)
+            st = srv.stats()
+        assert all(i["status"] == 0 and i["state"] == 3 for i in infos)
+        if mode == "batched":
+            assert st["max_batch_requests_seen"] > 1, st
+        for r, a in zip(reqs, alone):
+            assert _same_bits(a, r["out"]), (mode, cap, r["kind"], r["v"].numel())

@@ -75,6 +75,30 @@ def test_u_integral_variant_meets_the_bar_on_the_fallback_region(lb, oracle):
     assert e.max() <= TOL64, e.max()
 
 
+def test_paper_integral_entry_point(lb, oracle):
+    """lbessel_log_kv_integral_f64 is the u_integral variant in the grouped
+    layout, bit for bit, and meets the binary64 bar on the stress grid's
+    distribution, on the paper's Small region and below x = 1e-10 (where its
+    600-node rule still runs for v >= 0.3)."""
+    from paper_2409_08729_amd import workloads as wl
+    v, x = _mixed()
+    dv, dx = torch.from_numpy(v).cuda(), torch.from_numpy(x).cuda()
+    y = lb.log_kv_integral(dv, dx)
+    ref = lb.eval_variant("K", "u_integral", "grouped", dv, dx)
+    assert torch.equal(_bits(y), _bits(ref))
+    g = np.random.default_rng(23)
+    vs, xs = wl.m3(20_000, seed=23)
+    vt = g.uniform(0.0, 14.0, 2000)
+    xt = 10 ** g.uniform(-300.0, -10.0, 2000)
+    v2, x2 = np.concatenate([vs, vt]), np.concatenate([xs, xt])
+    y2 = lb.log_kv_integral(torch.from_numpy(v2).cuda(), torch.from_numpy(x2).cuda())
+    hi, lo = oracle.log_kv(v2, x2)
+    e = cond_err(y2.cpu().numpy(), hi, lo, v2, x2)
+    assert e.max() <= TOL64, (e.max(), v2[e.argmax()], x2[e.argmax()])
+    with pytest.raises(lb.LbesselError):
+        lb.log_kv_integral(dv.float(), dx.float())
+
+
 def test_simpson_variant_is_the_paper_rule(lb, oracle):
     # composite Simpson on the same 600 nodes: correct normalisation (no log 2
     # offset), but a discretisation error far above the Gregory rule's at small
