@@ -337,15 +337,16 @@ def ablation_bench(lb, torch, sets, sample=1 << 13):
 
 
 def order01_bench(lb, torch, n=20_000_000):
-    """Orders 0 and 1 (the paper's v = 0, 1 comparisons): the scalar-order fast
-    path against the general path on the same arguments, x ~ U[0, 150) (the
-    paper's Small region) and x ~ U[150, 1e4) (Large), binary64."""
+    """Orders 0 and 1 (the paper's v = 0, 1 comparisons) and the integer
+    orders 2, 4, 8 of the per-order set: the scalar-order path against the
+    general path on the same arguments, x ~ U[0, 150) (the paper's Small
+    region) and x ~ U[150, 1e4) (Large), binary64."""
     g = torch.Generator(device="cuda:0")
     g.manual_seed(20240917)
     res = {}
     for region, lo, hi in (("small", 0.0, 150.0), ("large", 150.0, 1e4)):
         x = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64) * (hi - lo) + lo
-        for v in (0.0, 1.0):
+        for v in (0.0, 1.0, 2.0, 4.0, 8.0):
             vv = torch.full_like(x, v)
             for kind in ("I", "K"):
                 f_fast = lb.log_iv_order if kind == "I" else lb.log_kv_order

@@ -1005,6 +1005,69 @@ __device__ __forceinline__ T order01(T x) {
 }
 
 // ---------------------------------------------------------------------------
+// Integer orders 2..14 (scalar-order path)
+// ---------------------------------------------------------------------------
+// Outside the series / integral region of order n the general branches apply
+// unchanged (same bits as the general path).  Inside it:
+//   I: log I_n = n log(x/2) - log n! + log1p(q h_n(q)), q = x^2/4, h_n the
+//      polynomial with the exact constant coefficients n!/(k!(k+n)!)
+//      (DLMF 10.25.2): no divisions and one trip count for every argument;
+//   K: the forward recurrence K_{j+1} = K_{j-1} + (2j/x) K_j (DLMF 10.29.1)
+//      from K_0 and K_1 of the order-0/1 path, on the ratios r_j = K_j/K_{j-1}:
+//      r_{j+1} = 1/r_j + 2j/x.  Both terms are positive, so nothing cancels,
+//      and the relative error of 1/r_j enters r_{j+1} damped by
+//      (1/r_j)/r_{j+1} < 1: about one rounding per step.  log K_n = log K_1 +
+//      log prod r_j, the product renormalised to [1/2, 1) at every step (its
+//      exponent counted apart), so no range limit.  Below x = 1e-10 the
+//      small-argument form of the general path.
+template <typename T> struct TabInt;
+template <> struct TabInt<double> {
+    static constexpr int terms = tables::kIIntTerms64;
+    static __device__ __forceinline__ const double *ser() { return &tables::kIIntSer64[0][0]; }
+    static __device__ __forceinline__ const double *logfact() { return tables::kLogFact64; }
+};
+template <> struct TabInt<float> {
+    static constexpr int terms = tables::kIIntTerms32;
+    static __device__ __forceinline__ const float *ser() { return &tables::kIIntSer32[0][0]; }
+    static __device__ __forceinline__ const float *logfact() { return tables::kLogFact32; }
+};
+
+template <typename T, int KIND>
+__device__ __forceinline__ T order_int(int n, T x) {
+    const T v = T(n);
+    const int b = classify<T, KIND>(v, x);
+    if (b == BR_MU)
+        return br_mu<T, KIND>(v, x);
+    if (b == BR_U) {
+        const int tr = u_tier(v);
+        return br_u<T, KIND>(v, x, (tr == 3) ? 4 : (tr == 2) ? 6 : (tr == 1) ? 9 : 13);
+    }
+    if (KIND == KIND_I) {
+        const T q = T(0.25) * x * x;
+        const LB_CONST_AS T *c =
+            opaque_const<T>(TabInt<T>::ser()) + (n - tables::kIntOrderMin) * TabInt<T>::terms;
+        const T qh = q * horner<T, TabInt<T>::terms>(c, q);
+        const T lf = opaque_const<T>(TabInt<T>::logfact())[n];
+        return v * (llog(x) - Cst<T>::ln2) - lf + llog1p(qh);
+    }
+    if (x < T(1e-10))
+        return T(br_k_small_x(double(v), double(x)));
+    const T l0 = order01<T, KIND_K, 0>(x);
+    const T l1 = order01<T, KIND_K, 1>(x);
+    const T ix2 = T(2) * lrcp(x);
+    T r = lexp(l1 - l0);   // K_1 / K_0
+    T m = T(1);
+    int e = 0;
+    for (int j = 1; j < n; ++j) {
+        r = fma(T(j), ix2, lrcp(r));
+        int ej;
+        m = frexp(m * r, &ej);
+        e += ej;
+    }
+    return l1 + fma(T(e), Cst<T>::ln2, llog(m));
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
 

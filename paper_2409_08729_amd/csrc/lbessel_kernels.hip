@@ -639,6 +639,20 @@ __global__ __launch_bounds__(kThreads) void k_order01(const T *__restrict__ x,
     out[i] = y;
 }
 
+// Integer orders 2..14: one element per thread (order_int).
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_order_int(int nu, const T *__restrict__ x,
+                                                        T *__restrict__ out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const T xx = x[i];
+    T y;
+    if (!special_value<T, KIND>(T(nu), xx, &y))
+        y = order_int<T, KIND>(nu, xx);
+    out[i] = y;
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics kernels
 // ---------------------------------------------------------------------------
@@ -1011,8 +1025,9 @@ int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out, in
 
 }  // extern "C"
 
-// Scalar order: orders 0 and 1 take the polynomial kernel, every other order
-// the grouped kernel with the order broadcast.
+// Scalar order: orders 0 and 1 take the polynomial kernel, integer orders
+// 2..14 the integer-order kernel, every other order the grouped kernel with
+// the order broadcast.
 template <typename T, int KIND>
 static int run_order(T v, const T *x, T *out, int64_t n, hipStream_t st) {
     if (n < 0)
@@ -1032,6 +1047,13 @@ static int run_order(T v, const T *x, T *out, int64_t n, hipStream_t st) {
         else
             hipLaunchKernelGGL((k_order01<T, KIND, 1>), dim3(blocks), dim3(kThreads), 0, st, x,
                                out, n);
+        return launch_status();
+    }
+    if (av == rint(av) && av >= T(tables::kIntOrderMin) && av <= T(tables::kIntOrderMax)) {
+        if (!grid_ok(n, kThreads, &blocks))
+            return LBESSEL_EINVAL;
+        hipLaunchKernelGGL((k_order_int<T, KIND>), dim3(blocks), dim3(kThreads), 0, st, int(av),
+                           x, out, n);
         return launch_status();
     }
     Args<T> a{nullptr, x, nullptr, out, n, v, T(0)};

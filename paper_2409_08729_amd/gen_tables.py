@@ -188,6 +188,36 @@ def i01_series(v: int) -> list[Fraction]:
     return [Fraction(1, math.factorial(k) * math.factorial(k + v)) for k in range(I01_TERMS)]
 
 
+# Integer orders 2..14 of the scalar-order path: I_n(x) = (x/2)^n/n! (1 +
+# sum_{k>=1} d_{n,k} q^k), d_{n,k} = n!/(k!(k+n)!), q = x^2/4 (DLMF 10.25.2),
+# on the series region of each order (x <= 23 in binary64, x <= 7.5 in
+# binary32); the term counts keep the neglected tail below 2^-60 (binary64)
+# and 2^-30 (binary32) of the sum there.
+INT_ORDERS = range(2, 15)
+IINT_TERMS64 = 40    # k = 1..40 (37 suffice at n = 2, x = 23)
+IINT_TERMS32 = 16    # (13 suffice at n = 2, x = 7.5)
+IINT_XMAX64 = Fraction(23)
+IINT_XMAX32 = Fraction(15, 2)
+
+
+def iint_series(n: int, terms: int) -> list[Fraction]:
+    f = math.factorial(n)
+    return [Fraction(f, math.factorial(k) * math.factorial(k + n)) for k in range(1, terms + 1)]
+
+
+def iint_tail_ok(n: int, terms: int, xmax: Fraction, bits: int) -> bool:
+    """The sum beyond the last kept term, bounded by the next term over
+    (1 - ratio) (terms decrease geometrically past k ~ sqrt(q)), below 2^-bits
+    of the sum at x = xmax."""
+    q = xmax * xmax / 4
+    d = iint_series(n, terms + 1)
+    nxt = d[terms] * q ** (terms + 1)
+    ratio = q / ((terms + 2) * (terms + 2 + n))
+    assert ratio < 1
+    total = 1 + sum(c * q ** (k + 1) for k, c in enumerate(d[:terms]))
+    return nxt / (1 - ratio) < total / Fraction(2) ** bits
+
+
 def _harmonic(k: int) -> Fraction:
     return sum((Fraction(1, j) for j in range(1, k + 1)), Fraction(0))
 
@@ -439,6 +469,31 @@ def render_header() -> str:
                                 ("kK1Ser32", to_f32_exact, f32_hex, "float")):
         lines.append(f"__constant__ const {ty} {name}[{K01_TERMS}] = {{"
                      + ", ".join(fmt(conv(c)) for c in k1a) + "};")
+    # integer orders 2..14: I_n series coefficients and log n!
+    for n in INT_ORDERS:
+        assert iint_tail_ok(n, IINT_TERMS64, IINT_XMAX64, 60), n
+        assert iint_tail_ok(n, IINT_TERMS32, IINT_XMAX32, 30), n
+    lines.append(f"constexpr int kIntOrderMin = {INT_ORDERS[0]};")
+    lines.append(f"constexpr int kIntOrderMax = {INT_ORDERS[-1]};")
+    lines.append(f"constexpr int kIIntTerms64 = {IINT_TERMS64};")
+    lines.append(f"constexpr int kIIntTerms32 = {IINT_TERMS32};")
+    lines.append("// I_n(x) = (x/2)^n / n! (1 + sum_k d[n-2][k-1] q^k), d = n!/(k!(k+n)!), k >= 1.")
+    for name, conv, fmt, ty, terms in (("kIIntSer64", to_f64, f64_hex, "double", IINT_TERMS64),
+                                       ("kIIntSer32", to_f32_exact, f32_hex, "float",
+                                        IINT_TERMS32)):
+        lines.append(f"__constant__ const {ty} {name}[{len(INT_ORDERS)}][{terms}] = {{")
+        for n in INT_ORDERS:
+            lines.append("    {" + ", ".join(fmt(conv(c)) for c in iint_series(n, terms)) + "},")
+        lines.append("};")
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 50
+        logfact = [Decimal(math.factorial(n)).ln() for n in range(INT_ORDERS[-1] + 1)]
+    lines.append("// log n!, n = 0..14.")
+    lines.append(f"__constant__ const double kLogFact64[{len(logfact)}] = {{"
+                 + ", ".join(f64_hex(dec_to_f64(d)) for d in logfact) + "};")
+    lines.append(f"__constant__ const float kLogFact32[{len(logfact)}] = {{"
+                 + ", ".join(f32_hex(dec_to_f32(d)) for d in logfact) + "};")
     lines.append("// Chebyshev coefficients of log K_v(x) + x + 1/2 log(2x/pi) in s = 1/x,")
     lines.append("// s in [1/17.5, 1/2] mapped to u in [-1, 1]; rows v = 0, 1.")
     cheb = [k01_chebyshev(0), k01_chebyshev(1)]

@@ -1,7 +1,10 @@
 """Scalar-order entry points: orders 0 and 1 take the polynomial fast path
 (checked against the binary128 oracle, f64 and f32, over the whole argument
-range and across every internal boundary); any other order runs the general
-path with v broadcast and must give the array path's bits."""
+range and across every internal boundary); integer orders 2..14 take the
+integer-order path (constant-coefficient I series, forward K recurrence from
+K_0 and K_1; oracle-checked, and equal to the general path's bits outside its
+series/integral region); any other order runs the general path with v
+broadcast and must give the array path's bits."""
 import numpy as np
 import pytest
 import torch
@@ -71,7 +74,7 @@ def test_other_orders_equal_array_path_bitwise(lb, kind, dtype):
     f_ord = lb.log_iv_order if kind == "I" else lb.log_kv_order
     f_arr = lb.log_iv if kind == "I" else lb.log_kv
     it = torch.int64 if dtype == torch.float64 else torch.int32
-    for v in (0.5, 2.0, 7.25, 30.0, 1e3):
+    for v in (0.5, 2.5, 7.25, 15.0, 30.0, 1e3):
         a = f_ord(v, x)
         b = f_arr(torch.full_like(x, v), x)
         assert torch.equal(a.view(it), b.view(it)), (kind, v)
@@ -103,3 +106,61 @@ def test_order_fast_path_huge_x(lb, kind):
         lead = (x - 0.5 * (np.log(2 * np.pi) + np.log(x)) if kind == "I"
                 else 0.5 * (np.log(np.pi / 2) - np.log(x)) - x)
         assert np.all(np.abs(y - lead) <= 4e-15 * np.abs(lead) + 1e-14), (kind, v, y, lead)
+
+
+INT_ORDERS = list(range(2, 15))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_integer_orders_match_oracle(lb, oracle, kind, dtype):
+    """Orders 2..14 on a seeded 700-point share of the argument grid each
+    (tiny, series/integral region, every internal boundary, Hankel/Debye
+    regions), against the binary128 oracle at the (f32-rounded) inputs."""
+    xs = _xgrid(5)
+    g = np.random.default_rng(6)
+    f = lb.log_iv_order if kind == "I" else lb.log_kv_order
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    for n in INT_ORDERS:
+        x = np.concatenate([g.choice(xs, 700, replace=False),
+                            [1e-10, np.nextafter(1e-10, 1), 2.0, 7.0, 7.5, 17.5, 20.0, 23.0]])
+        if kind == "I" and dtype == torch.float32:
+            x = x[x <= 700.0]
+        if dtype == torch.float32:
+            x = x.astype(np.float32)
+            x = x[(x > 0) & np.isfinite(x)]
+        y = f(float(n), torch.from_numpy(x).to("cuda:0")).cpu().numpy()
+        xd = x.astype(np.float64)
+        vd = np.full(xd.size, float(n))
+        hi, lo = (oracle.log_iv if kind == "I" else oracle.log_kv)(vd, xd)
+        fin = np.isfinite(hi)
+        assert np.array_equal(np.isfinite(y), fin), (kind, n)
+        e = cond_err(y.astype(np.float64)[fin], hi[fin], lo[fin], vd[fin], xd[fin])
+        assert e.max() <= tol, (kind, n, dtype, e.max(), xd[fin][int(np.argmax(e))])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["I", "K"])
+def test_integer_orders_outside_their_region_equal_general_path(lb, kind, dtype):
+    """Where the general path runs the Hankel or Debye branch for order n,
+    the integer-order path runs the same code: same bits; also the special
+    values and negative orders for K."""
+    x = torch.from_numpy(_xgrid(7)).to("cuda:0", dtype)
+    f_ord = lb.log_iv_order if kind == "I" else lb.log_kv_order
+    f_arr = lb.log_iv if kind == "I" else lb.log_kv
+    it = torch.int64 if dtype == torch.float64 else torch.int32
+    for n in INT_ORDERS:
+        vv = torch.full_like(x, float(n))
+        br = lb.classify(kind, vv, x)
+        keep = br != 2                     # Hankel, Debye or special value
+        a = f_ord(float(n), x)
+        b = f_arr(vv, x)
+        assert torch.equal(a[keep].view(it), b[keep].view(it)), (kind, n)
+        if kind == "K":
+            assert torch.equal(lb.log_kv_order(-float(n), x).view(it), a.view(it))
+    sp = torch.tensor([0.0, np.inf, np.nan, -1.0], dtype=dtype, device="cuda:0")
+    for n in (2, 14):
+        y = f_ord(float(n), sp).cpu().numpy()
+        ref = f_arr(torch.full_like(sp, float(n)), sp).cpu().numpy()
+        assert np.array_equal(np.isnan(y), np.isnan(ref)) and np.array_equal(
+            np.nan_to_num(y), np.nan_to_num(ref)), (kind, n, y, ref)
