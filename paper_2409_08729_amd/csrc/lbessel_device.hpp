@@ -647,9 +647,10 @@ __device__ __forceinline__ double br_k_small_x(double v, double x) {
 // integrand is even in t and entire, and decays double-exponentially, so the
 // trapezoid rule with step h converges geometrically: its error is the
 // integrand's Fourier transform at 2 pi / h, ~ K_{v + 2 pi i / h}(x), and
-// h = min(0.22 / (1 + v/20), 0.5 / sqrt(x cosh t*)) keeps it below 1e-16
+// h = min(0.25 / (1 + v/20), 0.5 / sqrt(x cosh t*)) keeps it below ~3e-16
 // relative on the whole fallback region (x <= 21, v <= 14.6; fitted against
-// the binary128 oracle with a margin).  Only nodes where the log-integrand is
+// the binary128 oracle: the first constant binds, and 0.27 would already
+// give 2.3e-15 near v = 3, x = 3.4).  Only nodes where the log-integrand is
 // within kDrop of its value at the peak t* are summed, which takes 10 to ~150
 // nodes instead of the 600 of the rule on the u-integral.  Node positions
 // are multiples of 1/64, so every t_j is exact and the only rounding in a
@@ -754,7 +755,7 @@ __device__ __forceinline__ double br_k_cosh(double v, double x, const KTab *kt,
     constexpr int kMaxNodes = 1024;         // every walk ends (window <= ~40 / h)
     // the shift, every term, both sums and the result are binary64
     int t0q, hq;
-    k_peak_step(float(v), float(x), v * v > x, 0.22f, 0.5f, t0q, hq);
+    k_peak_step(float(v), float(x), v * v > x, 0.25f, 0.5f, t0q, hq);
     const double h = hq * kGrid;
     // shift M = log-integrand at t0 = t0q/64 in binary64 (log cosh(vt) =
     // vt + log1p(e^{-2vt}) - ln 2), e^{+-t0} from the node tables
@@ -919,7 +920,7 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
         const float a = 45.0f * fm::rcp_hw(xf);
         w = fm::log_hw(1.0f + a + fm::sqrt_hw(a * (2.0f + a)));   // acosh(1 + 45/x)
     }
-    const float est = w * fmaf(0.05f, vf, 1.0f) * (1.0f / 0.22f);
+    const float est = w * fmaf(0.05f, vf, 1.0f) * (1.0f / 0.25f);
     return (est < 19.0) ? 0 : (est < 29.0) ? 1 : (est < 37.0) ? 2 : (est < 45.0) ? 3
                                                                  : (est < 55.0) ? 4 : 5;
 }

@@ -68,6 +68,6 @@ def test_walks_end_inside_the_node_tables():
     worst = 0.0
     for x in np.geomspace(1e-10, 60.0, 40):
         for v in np.concatenate([[0.0], np.geomspace(1e-4, 16.0, 30)]):
-            for kdrop, cv, cs in ((40.0, 0.22, 0.5), (18.0, 0.44, 1.0)):   # binary64, binary32 rules
+            for kdrop, cv, cs in ((40.0, 0.25, 0.5), (18.0, 0.44, 1.0)):   # binary64, binary32 rules
                 worst = max(worst, _largest_node(float(v), float(x), kdrop, cv, cs))
     assert worst < T_TABLE - 2.0, worst
