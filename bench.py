@@ -90,10 +90,15 @@ def one_step(lb, torch, sets, outs, timers=None):
 U_TIER_CUTS = (26.0, 60.0, 190.0)
 
 
+# integer orders of the K fallback that run the integer-order path (x >= 1e-10)
+K_INT_ORDER_MAX = 14
+
+
 def op_counts(lb, torch, sets):
     """Branch mix of every set (lbessel_classify; Debye elements split by
-    term-count tier) and the total integrand node count of the K fallback
-    elements (lbessel_k_nodes) for the op model."""
+    term-count tier; K fallback elements of integer order 0..14 at x >= 1e-10
+    counted per order and side of x = 2) and the total integrand node count of
+    the K fallback elements (lbessel_k_nodes) for the op model."""
     mix, nodes = {}, {}
     cuts = torch.tensor(U_TIER_CUTS, dtype=sets[0][1].dtype, device=sets[0][1].device)
     for j, (name, v, x) in enumerate(sets):
@@ -105,8 +110,30 @@ def op_counts(lb, torch, sets):
             c_u = torch.bincount(tiers, minlength=4).cpu().tolist()
             mix[(j, kind)] = {"mu20": c[0], "u13": c_u[0], "u9": c_u[1], "u6": c_u[2],
                               "u4": c_u[3], "fallback": c[2], "special": c[3]}
+            if kind == "K":
+                va = v.abs()
+                m = (b == 2) & (x >= 1e-10) & (va <= K_INT_ORDER_MAX) & (va == torch.round(va))
+                for side, sm in (("int_le2", x <= 2.0), ("int_gt2", x > 2.0)):
+                    n_of = va[m & sm].to(torch.int64)
+                    mix[(j, kind)][side] = torch.bincount(
+                        n_of, minlength=K_INT_ORDER_MAX + 1).cpu().tolist()
         nodes[j] = int(lb.k_nodes(v, x).to(torch.int64).sum().item())
     return mix, nodes
+
+
+def k_int_ops(c, ck):
+    """Ops and element count of the integer-order K fallback elements of one
+    launch (op model entries int_le2 / int_gt2, per order)."""
+    ops, cnt = 0.0, 0
+    for side in ("int_le2", "int_gt2"):
+        per = ck.get(side) or []
+        for n, k in enumerate(c.get(side, [])):
+            if k:
+                if n >= len(per) or per[n] is None:
+                    raise SystemExit(f"op model has no {side} entry for order {n}")
+                ops += k * per[n]
+                cnt += k
+    return ops, cnt
 
 
 def cpu_baseline(sets_host, seconds_target=12.0):
@@ -660,7 +687,8 @@ def main():
                           "k_grouped<double, K, log> (lbessel_log_kv_f64)",
                           f"{stress}: {sets[js][1].numel()} pairs", sets[js][1].numel(), 24,
                           "log_kv_f64_stress")
-    roof["branch_counts"] = mix[(js, "K")]
+    roof["branch_counts"] = {k: c for k, c in mix[(js, "K")].items()
+                             if not (isinstance(c, list) and not any(c))}
     roof["fallback_nodes"] = knodes[js]
     all_k_ops = sum(ops64[(j, "K")] for j in range(len(sets)))
     all_k_ms = sum(kern[f"K:{nm}"]["ms"] for nm, _, _ in sets)
@@ -860,10 +888,11 @@ def launch_table(per, sets, mix, knodes, om, prec):
         ops = {}
         for j in range(len(sets)):
             c = mix[(j, "K")]
+            int_ops, n_int = k_int_ops(c, ck)
             ops[(j, "K")] = (c["mu20"] * ck["mu20"]
                              + sum(c[u] * ck[u] for u in ("u13", "u9", "u6", "u4"))
-                             + c["fallback"] * ck["fallback_setup"]
-                             + knodes[j] * ck["fallback_per_node"])
+                             + (c["fallback"] - n_int) * ck["fallback_setup"]
+                             + knodes[j] * ck["fallback_per_node"] + int_ops)
             c = mix[(j, "I")]
             ops[(j, "I")] = (c["mu20"] * ci["mu20"]
                              + sum(c[u] * ci[u] for u in ("u13", "u9", "u6", "u4"))
@@ -892,7 +921,8 @@ def roofline_block(ops, ms, kernel, launch, n, bytes_per_pair, counter_label):
            "kernel": kernel, "launch": launch, "launch_ms": ms, "ops_per_launch": ops,
            "algorithmic_bytes_per_launch": bytes_per_pair * n,
            "op_model": "mu20 x n_mu + sum over Debye tiers uK x n_uK + fallback_setup x n_fb"
-                       " + fallback_per_node x nodes (paper_2409_08729_amd/opmodel.json)"}
+                       " + fallback_per_node x nodes + integer-order K elements at their"
+                       " per-order cost int_le2/int_gt2 (paper_2409_08729_amd/opmodel.json)"}
     if c is not None:
         rec["valu_busy"] = c["valu_busy"]
         rec["active_lanes"] = c["active_lanes"]

@@ -77,7 +77,10 @@ int lbessel_log_iv_f32(const float *v, const float *x, float *out,
 
 /*
  * out[i] = log K_{v[i]}(x[i]); same structure.  Small-argument branch (the
- * paper's fallback of Algorithm 1): for x >= 1e-10 the trapezoid rule on
+ * paper's fallback of Algorithm 1): for integer orders 0..14 the
+ * integer-order path of lbessel_log_kv_order_f64 (the order-0/1 expansions,
+ * then the recurrence K_{j+1} = K_{j-1} + (2j/x) K_j); otherwise, for
+ * x >= 1e-10 the trapezoid rule on
  * K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9), summed in
  * log scale over the nodes within a fixed drop of the integrand's peak; for
  * x < 1e-10 the two leading terms of K_v = pi (I_{-v} - I_v) / (2 sin v pi)
@@ -313,7 +316,8 @@ int lbessel_classify(int kind, int precision, const void *v, const void *x,
 /*
  * Integrand evaluations the log K fallback spends on each element (for the
  * op model of the benchmark): the node count of its integral rule, 0 for
- * elements of another branch or sub-case.  precision 64 or 32.
+ * elements of another branch or sub-case (integer orders 0..14 and x < 1e-10
+ * run closed expansions).  precision 64 or 32.
  */
 int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
                     int64_t n, void *stream);

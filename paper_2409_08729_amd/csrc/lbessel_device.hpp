@@ -877,9 +877,16 @@ __device__ __forceinline__ int u_tier(T v) {
     return (v > T(190)) ? 3 : (v > T(60)) ? 2 : (v > T(26)) ? 1 : 0;
 }
 
+// Integer orders whose K fallback (x >= 1e-10) runs the integer-order path
+// (order_int_fb) instead of the integral: 0 <= v <= 14, v integral.
+template <typename T>
+__device__ __forceinline__ bool int_order(T v) {
+    return v <= T(tables::kIntOrderMax) && v == rint(v);
+}
+
 // Cost bucket 0..B-1 of an I series element: its term count grows with x
-// (about 3 terms below x = 0.01, 8 at x = 1, 18 at x = 6, 33 at x = 20).
-// Only used to order work inside a tile; any value is correct.
+// (about 3 terms below x = 0.01, 8 at x = 1, 18 at x = 6, 33 at x = 20).  Only used to order work
+// inside a tile; any value is correct.
 template <int B, typename T>
 __device__ __forceinline__ int i_cost_bucket(T x) {
     static_assert(B == 4, "thresholds are set for four buckets");
@@ -895,6 +902,8 @@ __device__ __forceinline__ int i_cost_bucket(T x) {
 template <int B>
 __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     static_assert(B == 7, "six cost buckets and the interior-window class");
+    if (x >= 1e-10 && int_order(v))   // integer-order path: no walk
+        return 0;
     // binary32 hardware approximations: only an ordering key (x >= 1e-10 on
     // this branch keeps v/x and 45/x in binary32 range; smaller x only ever
     // lands in the last bucket)
@@ -1033,16 +1042,15 @@ template <> struct TabInt<float> {
     static __device__ __forceinline__ const float *logfact() { return tables::kLogFact32; }
 };
 
+// The fallback region's part for integer order n, 0 <= n <= 14 (orders 0 and
+// 1 by their fast path, whose expansions cover the whole fallback region).
 template <typename T, int KIND>
-__device__ __forceinline__ T order_int(int n, T x) {
+__device__ __forceinline__ T order_int_fb(int n, T x) {
     const T v = T(n);
-    const int b = classify<T, KIND>(v, x);
-    if (b == BR_MU)
-        return br_mu<T, KIND>(v, x);
-    if (b == BR_U) {
-        const int tr = u_tier(v);
-        return br_u<T, KIND>(v, x, (tr == 3) ? 4 : (tr == 2) ? 6 : (tr == 1) ? 9 : 13);
-    }
+    if (n == 0)
+        return order01<T, KIND, 0>(x);
+    if (n == 1)
+        return order01<T, KIND, 1>(x);
     if (KIND == KIND_I) {
         const T q = T(0.25) * x * x;
         const LB_CONST_AS T *c =
@@ -1068,6 +1076,19 @@ __device__ __forceinline__ T order_int(int n, T x) {
     return l1 + fma(T(e), Cst<T>::ln2, llog(m));
 }
 
+template <typename T, int KIND>
+__device__ __forceinline__ T order_int(int n, T x) {
+    const T v = T(n);
+    const int b = classify<T, KIND>(v, x);
+    if (b == BR_MU)
+        return br_mu<T, KIND>(v, x);
+    if (b == BR_U) {
+        const int tr = u_tier(v);
+        return br_u<T, KIND>(v, x, (tr == 3) ? 4 : (tr == 2) ? 6 : (tr == 1) ? 9 : 13);
+    }
+    return order_int_fb<T, KIND>(n, x);
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
@@ -1075,7 +1096,9 @@ __device__ __forceinline__ T order_int(int n, T x) {
 // Value of the given branch, in the precision T, except the K fallback below
 // x = 1e-10 (binary64 for both precisions).  K fallback: the cosh-integral
 // trapezoid for x >= 1e-10; below, the small-argument forms (br_k_tiny_x for
-// v < 0.3, br_k_small_x above).  The u-integral variants take the paper's
+// v < 0.3, br_k_small_x above).  Integer orders 0..14 take the
+// integer-order path for x >= 1e-10 instead: K_0, K_1 by their fast path and
+// K_n by the recurrence from them.  The u-integral variants take the paper's
 // 600-node rule for x >= 1e-10 and for x < 1e-10 with v >= 0.3.
 template <typename T, int KIND, int VAR = VAR_DEFAULT>
 __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND, T> *kt) {
@@ -1100,10 +1123,15 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND, T> *
         return br_u<T, KIND>(v, x);
     }
     if constexpr (KIND == KIND_I) {
+        // (integer orders keep the series here: the unrolled constant-
+        // coefficient polynomials of the scalar-order path need more
+        // registers than the grouped I kernels hold at full occupancy)
         return br_series_i<T>(v, x, kt);
     } else {
     constexpr bool u_integral = (VAR == VAR_U_INTEGRAL || VAR == VAR_SIMPSON || VAR == VAR_PAPER);
     if (!u_integral && x >= T(1e-10)) {
+        if (VAR == VAR_DEFAULT && int_order(v))
+            return order_int_fb<T, KIND_K>(int(v), x);
         if constexpr (std::is_same<T, float>::value)
             return br_k_cosh32(v, x, kt);
         else

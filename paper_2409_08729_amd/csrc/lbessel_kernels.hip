@@ -669,8 +669,8 @@ __global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, u
 }
 
 // Integrand evaluations of the K fallback per element: the node count of the
-// cosh-integral rule, 600 for the u-integral rule (x < 1e-10, v >= 0.3),
-// 0 for every other branch, special value or sub-case.
+// cosh-integral rule; 0 for every other branch, special value or sub-case
+// (integer orders and x < 1e-10 run closed expansions).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int32_t *nodes,
                                                      int64_t n) {
@@ -681,15 +681,13 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
     const T vv = fabs(v[i]), xx = x[i];
     T y;
     int c = 0;
-    if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB) {
-        if (xx >= T(1e-10)) {
-            if constexpr (std::is_same<T, float>::value)
-                br_k_cosh32(vv, xx, kt, &c);
-            else
-                br_k_cosh(vv, xx, kt, &c);
-        }
-        else if (vv >= T(0.3))
-            c = tables::kQuadN;
+    // integer orders and x < 1e-10 take closed expansions, no integral
+    if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB &&
+        xx >= T(1e-10) && !int_order(vv)) {
+        if constexpr (std::is_same<T, float>::value)
+            br_k_cosh32(vv, xx, kt, &c);
+        else
+            br_k_cosh(vv, xx, kt, &c);
     }
     nodes[i] = c;
 }

@@ -11,7 +11,9 @@ reports the VALU instructions one evaluation issues with no divergence
 (per element = SQ_INSTS_VALU / SQ_WAVES: all 64 lanes of every wave run the
 same branch on the same input).  The probe writes the integrand node count of
 each K fallback point (lbessel_k_nodes) to the JSON file.  The set "quad"
-probes the paper's own 600-node integral (the u_integral variant).
+probes the paper's own 600-node integral (the u_integral variant); the set
+"int" the integer-order path of the K fallback (orders 0..14, one point with
+x <= 2 and one above, where the order-0/1 expansions switch form).
 
 Reduce (host):
 
@@ -33,11 +35,16 @@ import sys
 
 # (precision, kind, branch, v, x): well inside each branch's region; the Debye
 # branch at one order per term-count tier (U_13, U_9, U_6, U_4); the K
-# fallback at points with different node counts.
-_FB_K64 = [(3.0, 5.0), (0.5, 1e-4), (12.0, 0.01), (1.0, 1.0), (6.0, 2.0), (0.1, 0.01),
-           (14.0, 10.0), (2.0, 15.0)]
-_FB_K32 = [(3.0, 5.0), (0.5, 1e-4), (8.0, 0.01), (1.0, 1.0), (6.0, 2.0), (0.1, 0.01),
-           (8.5, 5.0), (2.0, 6.5)]
+# fallback at points with different node counts (non-integer orders: integer
+# orders up to 14 take the integer-order path, probed apart).
+_FB_K64 = [(3.3, 5.0), (0.5, 1e-4), (12.3, 0.01), (1.1, 1.0), (6.2, 2.0), (0.1, 0.01),
+           (13.7, 10.0), (2.2, 15.0)]
+_FB_K32 = [(3.3, 5.0), (0.5, 1e-4), (8.1, 0.01), (1.1, 1.0), (6.2, 2.0), (0.1, 0.01),
+           (8.5, 5.0), (2.2, 6.5)]
+# integer orders of the K fallback region: 0..14 in binary64, 0..9 in binary32
+# (above 9 the binary32 classifier takes the Debye branch at every x)
+INT_X = (1.0, 5.0)
+INT_MAX = {64: 14, 32: 9}
 SETS = {
     "f64": [(64, k, b, v, x) for k in ("I", "K") for b, v, x in
             [(0, 3.0, 40.0), (1, 20.0, 10.0), (1, 40.0, 10.0), (1, 100.0, 10.0),
@@ -52,6 +59,8 @@ SETS = {
     # element per thread, no grouping); the per-element count is the same at
     # every point of the fallback region (fixed node count)
     "quad": [(64, "K", "u_integral", 3.0, 5.0), (64, "K", "u_integral", 0.5, 1e-4)],
+    "int": [(p, "K", 2, float(n), x) for p in (64, 32) for x in INT_X
+            for n in range(INT_MAX[p] + 1)],
 }
 U_TIER_NAMES = {20.0: "u13", 40.0: "u9", 100.0: "u6", 400.0: "u4"}
 NAMES = {0: "mu20", 2: "fallback"}
@@ -103,7 +112,9 @@ def reduce(path: str, points_json: str) -> dict:
                      "SQ_INSTS_VALU / SQ_WAVES of the probe dispatches of "
                      "paper_2409_08729_amd/opcount.py.  K fallback: setup + per_node x nodes "
                      "(least squares over the probe points).  quad600_per_eval: the paper's "
-                     "600-node integral (u_integral variant), per fallback evaluation.")
+                     "600-node integral (u_integral variant), per fallback evaluation.  "
+                     "int_le2 / int_gt2: the integer-order path of the K fallback, per order "
+                     "0.. (x <= 2 and x > 2).")
     fbs: dict = {}
     for d, (name, prec, kind, b, v0, x0), c in zip(ids, pts, nodes):
         per = disp[d]["SQ_INSTS_VALU"] / disp[d]["SQ_WAVES"]
@@ -115,6 +126,11 @@ def reduce(path: str, points_json: str) -> dict:
             model[key]["quad600_probes"].append({"v": v0, "x": x0, "valu": per})
             model[key]["quad600_per_eval"] = float(np.mean(
                 [q["valu"] for q in model[key]["quad600_probes"]]))
+            continue
+        if name == "int":
+            lst = model.setdefault(key, {}).setdefault("int_le2" if x0 <= 2.0 else "int_gt2", [])
+            lst.extend([None] * (int(v0) + 1 - len(lst)))
+            lst[int(v0)] = per
             continue
         if (kind, b) == ("K", 2):
             fbs.setdefault(key, []).append((c, per, v0, x0))

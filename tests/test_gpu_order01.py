@@ -4,7 +4,9 @@ range and across every internal boundary); integer orders 2..14 take the
 integer-order path (constant-coefficient I series, forward K recurrence from
 K_0 and K_1; oracle-checked, and equal to the general path's bits outside its
 series/integral region); any other order runs the general path with v
-broadcast and must give the array path's bits."""
+broadcast and must give the array path's bits.  The array path of log K runs
+the same integer-order code for integer orders 0..14 at x >= 1e-10, also
+inside tiles that mix them with other orders."""
 import numpy as np
 import pytest
 import torch
@@ -164,3 +166,41 @@ def test_integer_orders_outside_their_region_equal_general_path(lb, kind, dtype)
         ref = f_arr(torch.full_like(sp, float(n)), sp).cpu().numpy()
         assert np.array_equal(np.isnan(y), np.isnan(ref)) and np.array_equal(
             np.nan_to_num(y), np.nan_to_num(ref)), (kind, n, y, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_k_array_path_integer_orders_in_mixed_tiles(lb, oracle, dtype):
+    """Integer orders 0..14 interleaved with non-integer orders (and orders
+    one ulp off an integer) in one array: oracle parity everywhere, and the
+    integer elements at x >= 1e-10 give the bits of the scalar-order path."""
+    g = np.random.default_rng(8)
+    n = 12000
+    x = _xgrid(9)
+    x = g.choice(x[x <= 1e12], n)
+    ints = g.integers(0, 15, n).astype(np.float64)
+    v = np.where(g.random(n) < 0.5, ints, g.uniform(0.0, 16.0, n))
+    near = g.random(n) < 0.05
+    v = np.where(near, np.nextafter(ints, 20.0), v)
+    np_dt = np.float64 if dtype == torch.float64 else np.float32
+    v = v.astype(np_dt)
+    x = x.astype(np_dt)
+    keep = (x > 0) & np.isfinite(x)
+    v, x = v[keep], x[keep]
+    dv = torch.from_numpy(v).to("cuda:0")
+    dx = torch.from_numpy(x).to("cuda:0")
+    y = lb.log_kv(dv, dx).cpu().numpy()
+    vd, xd = v.astype(np.float64), x.astype(np.float64)
+    hi, lo = oracle.log_kv(vd, xd)
+    fin = np.isfinite(hi)
+    assert np.array_equal(np.isfinite(y), fin)
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    e = cond_err(y.astype(np.float64)[fin], hi[fin], lo[fin], vd[fin], xd[fin])
+    assert e.max() <= tol, (dtype, e.max(), vd[fin][int(np.argmax(e))], xd[fin][int(np.argmax(e))])
+    it = torch.int64 if dtype == torch.float64 else torch.int32
+    for k in range(15):
+        m = (v == k) & (x >= 1e-10)
+        if not m.any():
+            continue
+        a = lb.log_kv_order(float(k), dx[torch.from_numpy(m).to("cuda:0")])
+        b = torch.from_numpy(y[m]).to("cuda:0")
+        assert torch.equal(a.view(it), b.view(it)), (k, dtype)
