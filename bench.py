@@ -23,6 +23,7 @@ latency and throughput at several offered loads.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -73,16 +74,42 @@ def make_inputs(torch, dev):
 
 
 def one_step(lb, torch, sets, outs, timers=None):
+    """One pass of log I and log K over every set; timers, if given, is an
+    iterator over pre-created (name, kind, start, end) event records, one per
+    launch in this order."""
     for j, (name, v, x) in enumerate(sets):
         for kind, fn in (("I", lb.log_iv), ("K", lb.log_kv)):
             if timers is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
+                _, _, e0, e1 = next(timers)
                 e0.record()
             outs[(j, kind)] = fn(v, x)
             if timers is not None:
                 e1.record()
-                timers.append((name, kind, e0, e1))
+
+
+def timed_steps(lb, torch, sets, outs, steps):
+    """steps passes between two device synchronisations.  The HIP events of
+    every launch are created before the timed region, and the cyclic garbage
+    collector is paused inside it (a collection over the bench's objects can
+    stall the launching thread for milliseconds).  Returns (wall seconds,
+    host seconds to issue the launches, event records)."""
+    timers = [(name, kind, torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True))
+              for _ in range(steps) for name, _, _ in sets for kind in ("I", "K")]
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = iter(timers)
+        for _ in range(steps):
+            one_step(lb, torch, sets, outs, it)
+        t_issue = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gc.enable()
+    return wall, t_issue, timers
 
 
 # Debye term-count tiers of the library (u_tier in lbessel_device.hpp):
@@ -117,6 +144,14 @@ def op_counts(lb, torch, sets):
                     n_of = va[m & sm].to(torch.int64)
                     mix[(j, kind)][side] = torch.bincount(
                         n_of, minlength=K_INT_ORDER_MAX + 1).cpu().tolist()
+                if v.dtype == torch.float64:
+                    # Temme-series elements: term counts and order steps
+                    tt = lb.k_terms(v, x).to(torch.int64)
+                    tm = tt > 0
+                    steps = (torch.round(va[tm]) - 1).clamp(min=0)
+                    mix[(j, kind)]["temme"] = int(tm.sum().item())
+                    mix[(j, kind)]["temme_terms"] = int(tt.sum().item())
+                    mix[(j, kind)]["temme_steps"] = int(steps.sum().item())
         nodes[j] = int(lb.k_nodes(v, x).to(torch.int64).sum().item())
     return mix, nodes
 
@@ -661,13 +696,7 @@ def main():
     torch.cuda.synchronize()
 
     log(f"timing {args.steps} steps")
-    timers = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        one_step(lb, torch, sets, outs, timers)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall, t_issue, timers = timed_steps(lb, torch, sets, outs, args.steps)
     ms_per_step = wall * 1e3 / args.steps
     evals = 2 * n_pairs
     value = evals * args.steps / wall / 1e9
@@ -720,19 +749,16 @@ def main():
         o32 = {}
         one_step(lb, torch, sets32, o32)
         torch.cuda.synchronize()
-        timers32 = []
         steps32 = max(args.steps, 3)
-        t = time.perf_counter()
-        for _ in range(steps32):
-            one_step(lb, torch, sets32, o32, timers32)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / steps32
+        wall32, issue32, timers32 = timed_steps(lb, torch, sets32, o32, steps32)
+        dt = wall32 / steps32
         per32 = {}
         for name, kind, e0, e1 in timers32:
             per32.setdefault((name, kind), []).append(e0.elapsed_time(e1))
         mix32, knodes32 = op_counts(lb, torch, sets32)
         kern32, ops32 = launch_table(per32, sets32, mix32, knodes32, om, "f32")
         f32 = {"value": evals / dt / 1e9, "unit": "G evals/s", "ms_per_step": dt * 1e3,
+               "host_issue_ms_per_step": issue32 * 1e3 / steps32,
                "steps": steps32, "kernels": kern32}
         if ops32 is not None:
             f32["roofline"] = roofline_block(
@@ -812,6 +838,7 @@ def main():
         "config": {"workload": workload, "pairs_per_step": n_pairs, "evals_per_step": evals},
         "roofline": roof, "cpu_baseline": cpu, "all_finite": finite,
         "max_err_on_oracle_sample": errors, "ms_I_per_step": i_ms, "ms_K_per_step": k_ms,
+        "host_issue_ms_per_step": t_issue * 1e3 / args.steps,
         "f32": f32, "paper_k": paper_k, "grouping_ablation": ablation, "ablations": ablations,
         "order01": order01, "paper_tables": paper_tables, "vmf": vmf_res, "serving": serving,
         "launch_cost": launch_cost,
@@ -889,10 +916,15 @@ def launch_table(per, sets, mix, knodes, om, prec):
         for j in range(len(sets)):
             c = mix[(j, "K")]
             int_ops, n_int = k_int_ops(c, ck)
+            n_tm = c.get("temme", 0)
+            tm_ops = 0.0
+            if n_tm:
+                tm_ops = (n_tm * ck["temme_setup"] + c["temme_terms"] * ck["temme_per_term"]
+                          + c["temme_steps"] * ck["temme_per_step"])
             ops[(j, "K")] = (c["mu20"] * ck["mu20"]
                              + sum(c[u] * ck[u] for u in ("u13", "u9", "u6", "u4"))
-                             + (c["fallback"] - n_int) * ck["fallback_setup"]
-                             + knodes[j] * ck["fallback_per_node"] + int_ops)
+                             + (c["fallback"] - n_int - n_tm) * ck["fallback_setup"]
+                             + knodes[j] * ck["fallback_per_node"] + int_ops + tm_ops)
             c = mix[(j, "I")]
             ops[(j, "I")] = (c["mu20"] * ci["mu20"]
                              + sum(c[u] * ci[u] for u in ("u13", "u9", "u6", "u4"))
@@ -922,7 +954,9 @@ def roofline_block(ops, ms, kernel, launch, n, bytes_per_pair, counter_label):
            "algorithmic_bytes_per_launch": bytes_per_pair * n,
            "op_model": "mu20 x n_mu + sum over Debye tiers uK x n_uK + fallback_setup x n_fb"
                        " + fallback_per_node x nodes + integer-order K elements at their"
-                       " per-order cost int_le2/int_gt2 (paper_2409_08729_amd/opmodel.json)"}
+                       " per-order cost int_le2/int_gt2 + Temme-series K elements at"
+                       " temme_setup + temme_per_term x terms + temme_per_step x order steps"
+                       " (paper_2409_08729_amd/opmodel.json)"}
     if c is not None:
         rec["valu_busy"] = c["valu_busy"]
         rec["active_lanes"] = c["active_lanes"]

@@ -77,16 +77,20 @@ int lbessel_log_iv_f32(const float *v, const float *x, float *out,
 
 /*
  * out[i] = log K_{v[i]}(x[i]); same structure.  Small-argument branch (the
- * paper's fallback of Algorithm 1): for integer orders 0..14 the
- * integer-order path of lbessel_log_kv_order_f64 (the order-0/1 expansions,
- * then the recurrence K_{j+1} = K_{j-1} + (2j/x) K_j); otherwise, for
- * x >= 1e-10 the trapezoid rule on
+ * paper's fallback of Algorithm 1), for x >= 1e-10: integer orders 0..14
+ * take the integer-order path of lbessel_log_kv_order_f64 (the order-0/1
+ * expansions, then the recurrence K_{j+1} = K_{j-1} + (2j/x) K_j); other
+ * orders, in binary64 at x <= 1.25, Temme's series for K_mu and K_{mu+1} at
+ * the fractional part mu = v - rint(v) followed by the same recurrence up to
+ * v (N. M. Temme, J. Comput. Phys. 19, 1975); otherwise (binary64 above
+ * x = 1.25, every binary32 case) the trapezoid rule on
  * K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9), summed in
- * log scale over the nodes within a fixed drop of the integrand's peak; for
+ * log scale over the nodes within a fixed drop of the integrand's peak.  For
  * x < 1e-10 the two leading terms of K_v = pi (I_{-v} - I_v) / (2 sin v pi)
  * (DLMF 10.27.4), rearranged for v < 0.3.  This replaces the paper's
  * 600-node rule on its own integral (eq. log Kv integral), which
- * lbessel_eval_variant keeps as LBESSEL_VAR_U_INTEGRAL / _SIMPSON / _PAPER.
+ * lbessel_log_kv_integral_f64 and lbessel_eval_variant (LBESSEL_VAR_U_INTEGRAL
+ * / _SIMPSON / _PAPER) keep.
  */
 int lbessel_log_kv_f64(const double *v, const double *x, double *out,
                        int64_t n, void *stream);
@@ -316,11 +320,33 @@ int lbessel_classify(int kind, int precision, const void *v, const void *x,
 /*
  * Integrand evaluations the log K fallback spends on each element (for the
  * op model of the benchmark): the node count of its integral rule, 0 for
- * elements of another branch or sub-case (integer orders 0..14 and x < 1e-10
- * run closed expansions).  precision 64 or 32.
+ * elements of another branch or sub-case (integer orders 0..14, x < 1e-10
+ * and, in binary64, the Temme series at x <= 1.25 run no integral).
+ * precision 64 or 32.
  */
 int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
                     int64_t n, void *stream);
+
+/*
+ * Series terms the binary64 log K fallback's Temme branch (1e-10 <= x <= 1.25,
+ * non-integer order) spends on each element, after its first term; 0 for
+ * elements of another branch or sub-case (for the op model of the
+ * benchmark, beside lbessel_k_nodes).  Device arrays of n elements; n = 0 is
+ * a no-op; LBESSEL_EINVAL for null pointers or n < 0.
+ */
+int lbessel_k_terms(const double *v, const double *x, int32_t *terms, int64_t n,
+                    void *stream);
+
+/*
+ * The library's binary64 elementary functions on the device, for testing
+ * their accuracy where the kernels run them: out[i] = f(a[i]) with op
+ * 0 = 1/a (hardware estimate and two Newton steps), 1 = exp(a), 2 = exp(a)
+ * for |a| < 1e9 (the form the branches use on bounded arguments),
+ * 3 = log(a), 4 = log(1 + a), a >= 0.  Device arrays of n elements; n = 0 is
+ * a no-op; LBESSEL_EINVAL for another op, null pointers or n < 0.
+ */
+int lbessel_elementary_f64(int op, const double *a, double *out, int64_t n,
+                           void *stream);
 
 /*
  * Evaluate every element with one forced branch (0, 1 or 2 as above)

@@ -64,6 +64,8 @@ def _load():
         "lbessel_vmf_log_norm_grad_f64": [vp, ctypes.c_double, vp, i64, vp],
         "lbessel_classify": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_k_nodes": [ctypes.c_int, vp, vp, vp, i64, vp],
+        "lbessel_k_terms": [vp, vp, vp, i64, vp],
+        "lbessel_elementary_f64": [ctypes.c_int, vp, vp, i64, vp],
         "lbessel_log_iv_order_f64": [ctypes.c_double, vp, vp, i64, vp],
         "lbessel_log_kv_order_f64": [ctypes.c_double, vp, vp, i64, vp],
         "lbessel_log_iv_order_f32": [ctypes.c_float, vp, vp, i64, vp],
@@ -392,6 +394,35 @@ def k_nodes(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     with torch.cuda.device(x.device):
         _check(_load().lbessel_k_nodes(prec, v.data_ptr(), x.data_ptr(), out.data_ptr(),
                                        x.numel(), _stream(x)), "lbessel_k_nodes")
+    return out
+
+
+ELEMENTARY = {"rcp": 0, "exp": 1, "exp_bounded": 2, "log": 3, "log1p": 4}
+
+
+def elementary(op: str, a: torch.Tensor) -> torch.Tensor:
+    """The library's binary64 elementary function `op` (see ELEMENTARY),
+    evaluated on the device (lbessel_elementary_f64)."""
+    (a,) = _prep(a)
+    if a.dtype != torch.float64:
+        raise LbesselError("elementary takes float64 tensors")
+    out = torch.empty_like(a)
+    with torch.cuda.device(a.device):
+        _check(_load().lbessel_elementary_f64(ELEMENTARY[op], a.data_ptr(), out.data_ptr(),
+                                              a.numel(), _stream(a)), "lbessel_elementary_f64")
+    return out
+
+
+def k_terms(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Temme-series terms of the float64 log K fallback per element (int32; 0
+    for elements that take another branch or sub-case)."""
+    v, x = _prep(v, x)
+    if x.dtype != torch.float64:
+        raise LbesselError("k_terms takes float64 tensors")
+    out = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    with torch.cuda.device(x.device):
+        _check(_load().lbessel_k_terms(v.data_ptr(), x.data_ptr(), out.data_ptr(), x.numel(),
+                                       _stream(x)), "lbessel_k_terms")
     return out
 
 

@@ -8,7 +8,11 @@
 //   series: power series of I_v summed in log scale, eqs. (Iv infinite
 //           series), (ak recurrence), (log Iv), truncated when the remaining
 //           terms fall below the working precision (text after eq. K);
-//   K fallback (the library's path): for x >= 1e-10 the trapezoid rule on
+//   K fallback (the library's path): for x >= 1e-10 integer orders 0..14
+//           by the order-0/1 expansions and the order recurrence
+//           (order_int_fb); other orders in binary64 at x <= 1.25 by
+//           Temme's series and the same recurrence (br_k_temme); otherwise
+//           the trapezoid rule on
 //           K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9)
 //           over the nodes within a fixed drop of the log-integrand's peak
 //           (br_k_cosh, br_k_cosh32); for x < 1e-10 the leading terms of
@@ -69,10 +73,11 @@ __device__ __forceinline__ float llog1p(float a) {
 }
 // exp of an argument known to satisfy |a| < 1e9
 __device__ __forceinline__ double lexp_b(double a) { return fm::exp64_bounded(a); }
-// reciprocal: Newton-refined hardware estimate in binary64 (<= 1 ulp); the
-// hardware v_rcp_f32 (1 ulp) in binary32, for normal arguments (the binary32
-// branches take it of x >= 7, v > 0.1, r >= 1 and series denominators >= 1)
-__device__ __forceinline__ double lrcp(double a) { return fm::rcp_nr(a); }
+// reciprocal: the hardware estimate with two Newton steps in binary64
+// (<= 1 ulp, fm::rcp64); the hardware v_rcp_f32 (1 ulp) in binary32, for
+// normal arguments (the binary32 branches take it of x >= 7, v > 0.1, r >= 1
+// and series denominators >= 1)
+__device__ __forceinline__ double lrcp(double a) { return fm::rcp64(a); }
 __device__ __forceinline__ float lrcp(float a) { return fm::rcp_hw(a); }
 __device__ __forceinline__ float lexp_b(float a) { return expf(a); }
 
@@ -885,8 +890,8 @@ __device__ __forceinline__ bool int_order(T v) {
 }
 
 // Cost bucket 0..B-1 of an I series element: its term count grows with x
-// (about 3 terms below x = 0.01, 8 at x = 1, 18 at x = 6, 33 at x = 20).  Only used to order work
-// inside a tile; any value is correct.
+// (about 3 terms below x = 0.01, 8 at x = 1, 18 at x = 6, 33 at x = 20).
+// Only used to order work inside a tile; any value is correct.
 template <int B, typename T>
 __device__ __forceinline__ int i_cost_bucket(T x) {
     static_assert(B == 4, "thresholds are set for four buckets");
@@ -898,8 +903,11 @@ __device__ __forceinline__ int i_cost_bucket(T x) {
 // for an interior window (the peak estimate stands more than 40 above the
 // integrand at t = 0), whose right and left walks would otherwise run one
 // after the other in chunks shared with the single walk of windows that
-// start at 0.  Only used to order work inside a tile; any value is correct.
-template <int B>
+// start at 0.  With TEMME (the binary64 default path) buckets 0..3 hold the
+// Temme-series elements (x <= 1.25) by term and order-step estimate, and
+// the integer orders; 4, 5 and 6 the integral's.  Only used to order work
+// inside a tile; any value is correct.
+template <int B, bool TEMME>
 __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     static_assert(B == 7, "six cost buckets and the interior-window class");
     if (x >= 1e-10 && int_order(v))   // integer-order path: no walk
@@ -908,6 +916,15 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     // this branch keeps v/x and 45/x in binary32 range; smaller x only ever
     // lands in the last bucket)
     const float vf = float(v), xf = fmaxf(float(x), 1e-30f);
+    if (TEMME && x <= tables::kTemmeX) {
+        // Temme's series: ~2.5 units per term (the term count grows with x)
+        // and one per order step above mu + 1; x < 1e-10 (small-argument
+        // forms, ~2 terms' worth) lands in the cheapest series bucket
+        const float nt = (xf < 1e-4f) ? 2.0f : (xf < 1e-2f) ? 3.5f : (xf < 0.1f) ? 5.5f
+                         : (xf < 0.4f) ? 7.5f : 10.0f;
+        const float est = fmaf(2.5f, nt, fmaxf(rintf(vf) - 1.0f, 0.0f));
+        return (est < 10.0f) ? 0 : (est < 16.0f) ? 1 : (est < 22.0f) ? 2 : 3;
+    }
     float w;
     if (v * v > x) {
         const float q = vf * fm::rcp_hw(xf);
@@ -930,6 +947,8 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
         w = fm::log_hw(1.0f + a + fm::sqrt_hw(a * (2.0f + a)));   // acosh(1 + 45/x)
     }
     const float est = w * fmaf(0.05f, vf, 1.0f) * (1.0f / 0.25f);
+    if (TEMME)   // integral elements above the series bound: x > 1.25 or x < 1e-10
+        return (x < 1e-10) ? 3 : (est < 33.0f) ? 4 : 5;
     return (est < 19.0) ? 0 : (est < 29.0) ? 1 : (est < 37.0) ? 2 : (est < 45.0) ? 3
                                                                  : (est < 55.0) ? 4 : 5;
 }
@@ -1023,13 +1042,10 @@ __device__ __forceinline__ T order01(T x) {
 //      polynomial with the exact constant coefficients n!/(k!(k+n)!)
 //      (DLMF 10.25.2): no divisions and one trip count for every argument;
 //   K: the forward recurrence K_{j+1} = K_{j-1} + (2j/x) K_j (DLMF 10.29.1)
-//      from K_0 and K_1 of the order-0/1 path, on the ratios r_j = K_j/K_{j-1}:
-//      r_{j+1} = 1/r_j + 2j/x.  Both terms are positive, so nothing cancels,
-//      and the relative error of 1/r_j enters r_{j+1} damped by
-//      (1/r_j)/r_{j+1} < 1: about one rounding per step.  log K_n = log K_1 +
-//      log prod r_j, the product renormalised to [1/2, 1) at every step (its
-//      exponent counted apart), so no range limit.  Below x = 1e-10 the
-//      small-argument form of the general path.
+//      from K_0 and K_1 of the order-0/1 path (k_up_ratio: values scaled to
+//      K_1 = 1, in binary64).  Both terms are positive, so nothing cancels:
+//      about one rounding per step.  log K_n = log K_1 + log(K_n / K_1).
+//      Below x = 1e-10 the small-argument form of the general path.
 template <typename T> struct TabInt;
 template <> struct TabInt<double> {
     static constexpr int terms = tables::kIIntTerms64;
@@ -1041,6 +1057,26 @@ template <> struct TabInt<float> {
     static __device__ __forceinline__ const float *ser() { return &tables::kIIntSer32[0][0]; }
     static __device__ __forceinline__ const float *logfact() { return tables::kLogFact32; }
 };
+
+// K_{mu+n} / K_{mu+1} by the recurrence K_{nu+1} = K_{nu-1} + (2 nu / x) K_nu
+// (DLMF 10.29.1), nu = mu + 1 .. mu + n - 1, on values scaled so that
+// K_{mu+1} = 1 (d = K_mu / K_{mu+1} on entry): one fma per step, no
+// reciprocal.  For mu >= -1/2 every term is positive (K grows with the
+// order), so nothing cancels and each step adds about one rounding.  In
+// binary64 for both precisions: the ratio stays in [1, ~1e160] for n <= 15
+// and x >= 1e-10 (each step at most 1 + 2 (mu + 14) / x), so it needs no
+// rescaling there.
+__device__ __forceinline__ double k_up_ratio(double d, double mu, int n, double x) {
+    const double ix2 = 2.0 * lrcp(x);
+    const double a0 = mu * ix2;
+    double kn = 1.0;
+    for (int j = 1; j < n; ++j) {
+        const double knew = fma(fma(double(j), ix2, a0), kn, d);
+        d = kn;
+        kn = knew;
+    }
+    return kn;
+}
 
 // The fallback region's part for integer order n, 0 <= n <= 14 (orders 0 and
 // 1 by their fast path, whose expansions cover the whole fallback region).
@@ -1063,17 +1099,83 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
         return T(br_k_small_x(double(v), double(x)));
     const T l0 = order01<T, KIND_K, 0>(x);
     const T l1 = order01<T, KIND_K, 1>(x);
-    const T ix2 = T(2) * lrcp(x);
-    T r = lexp(l1 - l0);   // K_1 / K_0
-    T m = T(1);
-    int e = 0;
-    for (int j = 1; j < n; ++j) {
-        r = fma(T(j), ix2, lrcp(r));
-        int ej;
-        m = frexp(m * r, &ej);
-        e += ej;
+    return l1 + T(llog(k_up_ratio(double(lexp(l0 - l1)), 0.0, n, double(x))));
+}
+
+// ---------------------------------------------------------------------------
+// K fallback for small arguments (binary64): Temme's series
+// ---------------------------------------------------------------------------
+// For 1e-10 <= x <= kTemmeX = 1.25 and a non-integer order v the binary64 log K
+// fallback takes K_mu and K_{mu+1} at the fractional part mu = v - n,
+// n = rint(v), |mu| <= 1/2, from Temme's series (N. M. Temme, J. Comput.
+// Phys. 19, 1975), with q = x^2/4, c_k = q^k / k!, s = mu ln(2/x):
+//   K_mu     = sum_k c_k f_k,
+//   K_{mu+1} = (2/x) sum_k c_k (p_k - k f_k),
+//   f_0 = (mu pi / sin mu pi) (cosh(s) G1(mu) + (sinh(s)/s) ln(2/x) G2(mu)),
+//   p_0 = (x/2)^-mu Gamma(1+mu) / 2,
+//   q_0 = (x/2)^mu Gamma(1-mu) / 2,
+//   f_k = (k f_{k-1} + p_{k-1} + q_{k-1}) / (k^2 - mu^2),
+//   p_k = p_{k-1} / (k - mu),  q_k = q_{k-1} / (k + mu),
+// (G1, G2, sin(pi mu)/(pi mu) as polynomials in mu^2, generated tables), the
+// sum stopped once a term's parts fall below 2^-56 of both sums (the c_k
+// fall faster than geometrically for x <= 1.25); then the upward recurrence
+// K_{nu+1} = K_{nu-1} + (2 nu / x) K_nu (DLMF 10.29.1) from nu = mu + 1 to v
+// (k_up_ratio), as in the integer-order path.  One reciprocal per term:
+// 1/(k - mu) = (k + mu)/(k^2 - mu^2) and likewise; 1/k from a table (k is the
+// same in every lane of a wave).
+// Cost ~150 + ~20 per term (2..11 terms) + ~8 per order step, against
+// ~290 + ~38 per node (20..70 nodes there) for the integral; the series is
+// independent of the integral representations (the paper's and DLMF 10.32.9).
+// nterms, if given, receives the number of series terms after f_0.
+__device__ __forceinline__ double br_k_temme(double v, double x, int *nterms = nullptr) {
+    const double n = rint(v);
+    const double mu = v - n;
+    const double t = mu * mu;
+    const double L = Cst<double>::ln2 - llog(x);             // ln(2/x) > 0
+    const double s = mu * L;
+    const double e = lexp_b(s);                               // (2/x)^mu
+    const double ie = lrcp(e);
+    const LB_CONST_AS double *G = opaque_const<double>(&tables::kTmG64[0][0]);
+    const double g1 = horner<double, tables::kTmGCoefs>(G, t);
+    const double g2 = horner<double, tables::kTmGCoefs>(G + tables::kTmGCoefs, t);
+    const double sinc = horner<double, tables::kTmSincTerms>(
+        opaque_const<double>(tables::kTmSinc64), t);
+    double shs;                                               // sinh(s)/s
+    if (fabs(s) < 1.0)
+        shs = horner<double, tables::kTmSinhTerms>(opaque_const<double>(tables::kTmSinh64), s * s);
+    else
+        shs = (e - ie) * (0.5 * lrcp(s));
+    const double ch = 0.5 * (e + ie);
+    double f = fma(g1, ch, shs * L * g2) * lrcp(sinc);
+    double p = 0.5 * e * lrcp(fma(-mu, g1, g2));               // 1/Gamma(1+mu) = G2 - mu G1
+    double q = 0.5 * ie * lrcp(fma(mu, g1, g2));               // 1/Gamma(1-mu) = G2 + mu G1
+    const double qx = 0.25 * x * x;
+    const LB_CONST_AS double *ik = opaque_const<double>(tables::kTmInvK64);
+    double c = 1.0, s0 = f, s1 = p, kk = 0.0;
+    int k = 0;
+    while (k < tables::kTmMaxTerms) {
+        ++k;
+        kk += 1.0;
+        const double d = lrcp(fma(kk, kk, -t));
+        f = fma(kk, f, p + q) * d;
+        c = c * qx * ik[k];
+        p = p * (kk + mu) * d;
+        q = q * (kk - mu) * d;
+        s0 = fma(c, f, s0);
+        s1 = fma(c, fma(-kk, f, p), s1);
+        const double eps = Cst<double>::series_eps;
+        if (c * fabs(f) <= eps * s0 && c * fma(kk, fabs(f), fabs(p)) <= eps * s1)
+            break;
     }
-    return l1 + fma(T(e), Cst<T>::ln2, llog(m));
+    if (nterms != nullptr)
+        *nterms = k;
+    if (n == 0.0)
+        return llog(s0);
+    const double k1 = s1 * (2.0 * lrcp(x));                  // K_{mu+1}
+    const double l1 = llog(k1);
+    if (n == 1.0)
+        return l1;
+    return l1 + llog(k_up_ratio(s0 * lrcp(k1), mu, int(n), x));
 }
 
 template <typename T, int KIND>
@@ -1132,10 +1234,13 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND, T> *
     if (!u_integral && x >= T(1e-10)) {
         if (VAR == VAR_DEFAULT && int_order(v))
             return order_int_fb<T, KIND_K>(int(v), x);
-        if constexpr (std::is_same<T, float>::value)
+        if constexpr (std::is_same<T, float>::value) {
             return br_k_cosh32(v, x, kt);
-        else
+        } else {
+            if (VAR == VAR_DEFAULT && x <= tables::kTemmeX)
+                return br_k_temme(v, x);
             return br_k_cosh(v, x, kt);
+        }
     }
     if (x < T(1e-10) && v < T(0.3))
         return T(br_k_tiny_x(double(v), double(x)));

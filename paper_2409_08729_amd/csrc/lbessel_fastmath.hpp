@@ -42,12 +42,26 @@ __host__ __device__ __forceinline__ float fma_c(float a, float b, float c) {
 #endif
 }
 
-// 1/d to ~2^-100 relative from the hardware reciprocal and one Newton step
-// (the host build divides).  Only used where the quotient feeds a small
-// correction term.
+// 1/d from the hardware reciprocal (v_rcp_f64: ~2^-24 relative, measured up
+// to 2.3e8 ulps) and one Newton step: ~2^-47 relative, up to ~9 ulps
+// measured (the host build divides).  Only used where the quotient feeds a
+// small correction term.
 __host__ __device__ __forceinline__ double rcp_nr(double d) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const double q = __builtin_amdgcn_rcp(d);
+    return fma(q, fma(-d, q, 1.0), q);
+#else
+    return 1.0 / d;
+#endif
+}
+
+// 1/d to within one ulp: the hardware reciprocal and two Newton steps (the
+// second squares the first one's ~2^-47 error away, leaving the rounding of
+// its final fma), for normal d with 1/d normal (the host build divides).
+__host__ __device__ __forceinline__ double rcp64(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double q = __builtin_amdgcn_rcp(d);
+    q = fma(q, fma(-d, q, 1.0), q);
     return fma(q, fma(-d, q, 1.0), q);
 #else
     return 1.0 / d;

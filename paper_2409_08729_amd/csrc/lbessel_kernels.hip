@@ -323,7 +323,9 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                     b0 = C::u0 + ((C::ub > 1) ? u_tier(v) : 0);
                 else
                     b0 = C::f0 + ((C::fb == 1) ? 0
-                                  : (KIND == KIND_K) ? k_cost_bucket<kKBuckets>(double(v), double(x))
+                                  : (KIND == KIND_K)
+                                      ? k_cost_bucket<kKBuckets, (std::is_same<T, double>::value &&
+                                                                  VAR == VAR_DEFAULT)>(double(v), double(x))
                                                      : i_cost_bucket<kIBuckets>(x));
             } else {
                 T ys;
@@ -670,7 +672,8 @@ __global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, u
 
 // Integrand evaluations of the K fallback per element: the node count of the
 // cosh-integral rule; 0 for every other branch, special value or sub-case
-// (integer orders and x < 1e-10 run closed expansions).
+// (integer orders, x < 1e-10 and, in binary64, the Temme series at
+// x <= 1.25 run no integral).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int32_t *nodes,
                                                      int64_t n) {
@@ -686,10 +689,38 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
         xx >= T(1e-10) && !int_order(vv)) {
         if constexpr (std::is_same<T, float>::value)
             br_k_cosh32(vv, xx, kt, &c);
-        else
+        else if (xx > tables::kTemmeX)
             br_k_cosh(vv, xx, kt, &c);
     }
     nodes[i] = c;
+}
+
+// The library's binary64 elementary functions, one per element (op 0
+// reciprocal, 1 exp, 2 exp of |a| < 1e9, 3 log, 4 log(1 + a)).
+__global__ __launch_bounds__(kThreads) void k_elementary(int op, const double *a, double *out,
+                                                         int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const double x = a[i];
+    out[i] = (op == 0) ? lrcp(x) : (op == 1) ? lexp(x) : (op == 2) ? lexp_b(x)
+             : (op == 3) ? llog(x) : llog1p(x);
+}
+
+// Series terms of the binary64 K fallback's Temme branch per element (after
+// f_0); 0 for every other branch, special value or sub-case.
+__global__ __launch_bounds__(kThreads) void k_kterms(const double *v, const double *x,
+                                                     int32_t *terms, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const double vv = fabs(v[i]), xx = x[i];
+    double y;
+    int c = 0;
+    if (!special_value<double, KIND_K>(vv, xx, &y) && classify<double, KIND_K>(vv, xx) == BR_FB &&
+        xx >= 1e-10 && xx <= tables::kTemmeX && !int_order(vv))
+        br_k_temme(vv, xx, &c);
+    terms[i] = c;
 }
 
 template <typename T, int KIND>
@@ -1091,6 +1122,36 @@ int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
     else
         hipLaunchKernelGGL(k_knodes<float>, dim3(blocks), dim3(kThreads), 0, st,
                            (const float *)v, (const float *)x, nodes, n);
+    return launch_status();
+}
+
+int lbessel_elementary_f64(int op, const double *a, double *out, int64_t n, void *s) {
+    if (n < 0 || op < 0 || op > 4)
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (a == nullptr || out == nullptr)
+        return LBESSEL_EINVAL;
+    uint32_t blocks;
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    hipLaunchKernelGGL(k_elementary, dim3(blocks), dim3(kThreads), 0, static_cast<hipStream_t>(s),
+                       op, a, out, n);
+    return launch_status();
+}
+
+int lbessel_k_terms(const double *v, const double *x, int32_t *terms, int64_t n, void *s) {
+    if (n < 0)
+        return LBESSEL_EINVAL;
+    if (n == 0)
+        return LBESSEL_OK;
+    if (v == nullptr || x == nullptr || terms == nullptr)
+        return LBESSEL_EINVAL;
+    uint32_t blocks;
+    if (!grid_ok(n, kThreads, &blocks))
+        return LBESSEL_EINVAL;
+    hipLaunchKernelGGL(k_kterms, dim3(blocks), dim3(kThreads), 0, static_cast<hipStream_t>(s),
+                       v, x, terms, n);
     return launch_status();
 }
 

@@ -385,6 +385,101 @@ def lgamma1p_poly(j: int, deg: int = LG_DEG, nodes: int = LG_NODES, prec: int = 
         return a
 
 
+# ----------------------------------------------------------------------------
+# Temme's series for K_mu(x), K_{mu+1}(x), |mu| <= 1/2 (the small-argument K
+# fallback, x <= 1.25): the even functions of mu it needs, as polynomials in
+# t = mu^2 on [0, 1/4]
+#   G1(mu) = (1/Gamma(1-mu) - 1/Gamma(1+mu)) / (2 mu),  G1(0) = -gamma,
+#   G2(mu) = (1/Gamma(1-mu) + 1/Gamma(1+mu)) / 2,       G2(0) = 1,
+# (1/Gamma(1 + mu) = G2 - mu G1, 1/Gamma(1 - mu) = G2 + mu G1), and
+#   sin(pi mu) / (pi mu) = sum_k (-1)^k pi^{2k} t^k / (2k+1)!  (Taylor, exact
+# up to the rounding of pi^2), whose reciprocal is the factor mu pi / sin(mu pi).
+# ----------------------------------------------------------------------------
+TM_X = Fraction(5, 4)   # x bound of the Temme branch
+TM_G_DEG = 8            # degree of G1, G2 in t
+TM_SINC_TERMS = 12      # sinc terms (t^0 .. t^11; next term < 1e-18 at t = 1/4)
+TM_SINH_TERMS = 10      # sinh(s)/s = sum s^{2k}/(2k+1)!, |s| < 1 (next term < 2e-20)
+TM_MAX_TERMS = 40       # cap of the series loop (x <= 1.25 stops by ~13 terms)
+
+
+def _dec_sin(z, prec):
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec + 10
+        z = Decimal(z)
+        term, acc, k = z, z, 1
+        while abs(term) > Decimal(10) ** -(prec + 5):
+            k += 2
+            term = -term * z * z / (k * (k - 1))
+            acc += term
+        return +acc
+
+
+def temme_g(t, prec: int = 60):
+    """(G1, G2) at mu = sqrt(t) > 0 in `prec`-digit decimals (log Gamma by
+    dec_lgamma; the difference of G1 loses ~log10(1/mu) of the extra digits)."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec + 20
+        mu = Decimal(t).sqrt()
+        rp = (-dec_lgamma(1 + mu, prec + 20)).exp()
+        rm = (-dec_lgamma(1 - mu, prec + 20)).exp()
+        g1 = (rm - rp) / (2 * mu)
+        g2 = (rm + rp) / 2
+    with localcontext() as ctx:
+        ctx.prec = prec
+        return +g1, +g2
+
+
+@functools.lru_cache(maxsize=None)
+def temme_g_poly(which: int, deg: int = TM_G_DEG, prec: int = 60):
+    """Monomial coefficients b_0..b_deg in t of the Chebyshev interpolant (at
+    deg + 8 points of [0, 1/4]) of G1 (which = 0) or G2 (which = 1)."""
+    from decimal import Decimal, localcontext
+    nodes = deg + 8
+    tmax = Decimal(1) / 4
+    with localcontext() as ctx:
+        ctx.prec = prec + 20
+        pi = Decimal(PI_50)
+        us = [_dec_cos(pi * (Decimal(k) + Decimal("0.5")) / nodes, prec + 20)
+              for k in range(nodes)]
+        fs = [temme_g(tmax / 2 * (1 + u), prec)[which] for u in us]
+        tk = [[Decimal(1)] * nodes, list(us)]
+        for m in range(2, deg + 1):
+            tk.append([2 * us[k] * tk[m - 1][k] - tk[m - 2][k] for k in range(nodes)])
+        cs = []
+        for m in range(deg + 1):
+            c = sum(fs[k] * tk[m][k] for k in range(nodes)) * 2 / nodes
+            cs.append(c / 2 if m == 0 else c)
+        tpoly = [[Decimal(1)], [Decimal(0), Decimal(1)]]
+        for m in range(2, deg + 1):
+            nxt = [Decimal(0)] * (m + 1)
+            for i, c in enumerate(tpoly[m - 1]):
+                nxt[i + 1] += 2 * c
+            for i, c in enumerate(tpoly[m - 2]):
+                nxt[i] -= c
+            tpoly.append(nxt)
+        a = [Decimal(0)] * (deg + 1)
+        for m in range(deg + 1):
+            for i, c in enumerate(tpoly[m]):
+                a[i] += cs[m] * c
+        # u = 8 t - 1
+        b = [Decimal(0)] * (deg + 1)
+        for i, ai in enumerate(a):
+            for j in range(i + 1):
+                b[j] += ai * math.comb(i, j) * Decimal(8) ** j * (-1) ** (i - j)
+    return tuple(b)
+
+
+def temme_sinc_series(terms: int = TM_SINC_TERMS, prec: int = 60):
+    """(-1)^k pi^{2k} / (2k+1)!, k = 0..terms-1 (decimals)."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = prec
+        pi2 = Decimal(PI_50) ** 2
+        return [(-1) ** k * pi2 ** k / math.factorial(2 * k + 1) for k in range(terms)]
+
+
 def _debye_arrays():
     polys = debye_polys(U_TERMS)
     rows = [debye_p_coeffs(k, polys) for k in range(1, U_TERMS + 1)]
@@ -527,6 +622,26 @@ def render_header() -> str:
     for j in range(LG_INTERVALS):
         lines.append("    {" + ", ".join(f64_hex(dec_to_f64(c)) for c in lgamma1p_poly(j)) + "},")
     lines.append("};")
+    lines.append("// Temme's series (K fallback, x <= kTemmeX): G1, G2 as polynomials in t = mu^2")
+    lines.append("// (index = power), sin(pi mu)/(pi mu) in t, sinh(s)/s in s^2.")
+    lines.append(f"constexpr double kTemmeX = {f64_hex(to_f64(TM_X))};")
+    lines.append(f"constexpr int kTmGCoefs = {TM_G_DEG + 1};")
+    lines.append(f"constexpr int kTmSincTerms = {TM_SINC_TERMS};")
+    lines.append(f"constexpr int kTmSinhTerms = {TM_SINH_TERMS};")
+    lines.append(f"constexpr int kTmMaxTerms = {TM_MAX_TERMS};")
+    lines.append(f"__constant__ const double kTmG64[2][{TM_G_DEG + 1}] = {{")
+    for which in (0, 1):
+        lines.append("    {" + ", ".join(f64_hex(dec_to_f64(c)) for c in temme_g_poly(which))
+                     + "},")
+    lines.append("};")
+    lines.append(f"__constant__ const double kTmSinc64[{TM_SINC_TERMS}] = {{"
+                 + ", ".join(f64_hex(dec_to_f64(c)) for c in temme_sinc_series()) + "};")
+    lines.append(f"__constant__ const double kTmInvK64[{TM_MAX_TERMS + 1}] = {{0, "
+                 + ", ".join(f64_hex(to_f64(Fraction(1, k))) for k in range(1, TM_MAX_TERMS + 1))
+                 + "};")
+    lines.append(f"__constant__ const double kTmSinh64[{TM_SINH_TERMS}] = {{"
+                 + ", ".join(f64_hex(to_f64(Fraction(1, math.factorial(2 * k + 1))))
+                             for k in range(TM_SINH_TERMS)) + "};")
     lines.append(f"constexpr double kEulerGamma64 = {f64_hex(dec_to_f64(Decimal(EULER_GAMMA_50)))};")
     lines.append(f"constexpr float kEulerGamma32 = {f32_hex(dec_to_f32(Decimal(EULER_GAMMA_50)))};")
     lines.append("")

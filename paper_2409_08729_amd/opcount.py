@@ -13,7 +13,10 @@ same branch on the same input).  The probe writes the integrand node count of
 each K fallback point (lbessel_k_nodes) to the JSON file.  The set "quad"
 probes the paper's own 600-node integral (the u_integral variant); the set
 "int" the integer-order path of the K fallback (orders 0..14, one point with
-x <= 2 and one above, where the order-0/1 expansions switch form).
+x <= 2 and one above, where the order-0/1 expansions switch form); the set
+"temme" the binary64 K fallback's Temme series (x <= 1.25), whose cost is
+fitted as setup + per_term x terms + per_step x order steps (terms from
+lbessel_k_terms, steps = max(rint(v) - 1, 0)).
 
 Reduce (host):
 
@@ -36,9 +39,14 @@ import sys
 # (precision, kind, branch, v, x): well inside each branch's region; the Debye
 # branch at one order per term-count tier (U_13, U_9, U_6, U_4); the K
 # fallback at points with different node counts (non-integer orders: integer
-# orders up to 14 take the integer-order path, probed apart).
-_FB_K64 = [(3.3, 5.0), (0.5, 1e-4), (12.3, 0.01), (1.1, 1.0), (6.2, 2.0), (0.1, 0.01),
-           (13.7, 10.0), (2.2, 15.0)]
+# orders up to 14 take the integer-order path, and binary64 x <= 1.25 the
+# Temme series, both probed apart).
+_FB_K64 = [(3.3, 5.0), (0.5, 1.5), (12.3, 1.3), (1.1, 2.5), (6.2, 2.0), (0.1, 3.0),
+           (13.7, 10.0), (2.2, 15.0), (9.5, 1.4), (14.4, 4.0)]
+# Temme points: term counts ~2..11 (x) times order steps 0..13 (v)
+_TM_K64 = [(0.3, 1e-4), (0.3, 0.01), (0.3, 0.3), (0.3, 1.2), (4.4, 1e-3), (4.4, 0.1),
+           (4.4, 1.0), (9.7, 1e-4), (9.7, 0.05), (9.7, 1.2), (14.3, 1e-3), (14.3, 0.5),
+           (1.6, 0.02), (7.2, 0.7)]
 _FB_K32 = [(3.3, 5.0), (0.5, 1e-4), (8.1, 0.01), (1.1, 1.0), (6.2, 2.0), (0.1, 0.01),
            (8.5, 5.0), (2.2, 6.5)]
 # integer orders of the K fallback region: 0..14 in binary64, 0..9 in binary32
@@ -61,6 +69,7 @@ SETS = {
     "quad": [(64, "K", "u_integral", 3.0, 5.0), (64, "K", "u_integral", 0.5, 1e-4)],
     "int": [(p, "K", 2, float(n), x) for p in (64, 32) for x in INT_X
             for n in range(INT_MAX[p] + 1)],
+    "temme": [(64, "K", 2, v, x) for v, x in _TM_K64],
 }
 U_TIER_NAMES = {20.0: "u13", 40.0: "u9", 100.0: "u6", 400.0: "u4"}
 NAMES = {0: "mu20", 2: "fallback"}
@@ -71,7 +80,7 @@ PROBE_KERNELS = ("k_branch", "k_ungrouped")
 def probe(points_json: str, sets: list[str], n: int = 1 << 18) -> None:
     import torch
     import paper_2409_08729_amd as lb
-    pts, nodes = [], []
+    pts, nodes, terms = [], [], []
     for name in sets:
         for prec, kind, b, v0, x0 in SETS[name]:
             dt = torch.float64 if prec == 64 else torch.float32
@@ -83,12 +92,15 @@ def probe(points_json: str, sets: list[str], n: int = 1 << 18) -> None:
                 lb.eval_branch(kind, b, v, x)
             torch.cuda.synchronize()
             c = int(lb.k_nodes(v[:1], x[:1]).item()) if (kind, b) == ("K", 2) else 0
+            tm = (int(lb.k_terms(v[:1], x[:1]).item())
+                  if (kind, b) == ("K", 2) and prec == 64 else 0)
             pts.append([name, prec, kind, b, v0, x0])
             nodes.append(c)
-            print(f"{name}: {kind} branch {b} at v={v0} x={x0}: {n} elements, {c} nodes",
-                  flush=True)
+            terms.append(tm)
+            print(f"{name}: {kind} branch {b} at v={v0} x={x0}: {n} elements, {c} nodes, "
+                  f"{tm} series terms", flush=True)
     with open(points_json, "w") as f:
-        json.dump({"points": pts, "nodes": nodes}, f)
+        json.dump({"points": pts, "nodes": nodes, "terms": terms}, f)
 
 
 def reduce(path: str, points_json: str) -> dict:
@@ -96,6 +108,7 @@ def reduce(path: str, points_json: str) -> dict:
     import numpy as np
     meta = json.load(open(points_json))
     pts, nodes = meta["points"], meta["nodes"]
+    terms = meta.get("terms", [0] * len(pts))
     rows = list(csv.DictReader(open(path)))
     disp: dict = {}
     for r in rows:
@@ -114,9 +127,11 @@ def reduce(path: str, points_json: str) -> dict:
                      "(least squares over the probe points).  quad600_per_eval: the paper's "
                      "600-node integral (u_integral variant), per fallback evaluation.  "
                      "int_le2 / int_gt2: the integer-order path of the K fallback, per order "
-                     "0.. (x <= 2 and x > 2).")
+                     "0.. (x <= 2 and x > 2).  temme_setup + temme_per_term x terms + "
+                     "temme_per_step x max(rint(v) - 1, 0): the binary64 Temme series.")
     fbs: dict = {}
-    for d, (name, prec, kind, b, v0, x0), c in zip(ids, pts, nodes):
+    tms: dict = {}
+    for d, (name, prec, kind, b, v0, x0), c, tm in zip(ids, pts, nodes, terms):
         per = disp[d]["SQ_INSTS_VALU"] / disp[d]["SQ_WAVES"]
         key = f"{kind}_f{prec}"
         if name == "quad":
@@ -126,6 +141,9 @@ def reduce(path: str, points_json: str) -> dict:
             model[key]["quad600_probes"].append({"v": v0, "x": x0, "valu": per})
             model[key]["quad600_per_eval"] = float(np.mean(
                 [q["valu"] for q in model[key]["quad600_probes"]]))
+            continue
+        if name == "temme":
+            tms.setdefault(key, []).append((tm, max(round(v0) - 1, 0), per, v0, x0))
             continue
         if name == "int":
             lst = model.setdefault(key, {}).setdefault("int_le2" if x0 <= 2.0 else "int_gt2", [])
@@ -147,6 +165,16 @@ def reduce(path: str, points_json: str) -> dict:
         model[key]["fallback_probes"] = [
             {"v": v0, "x": x0, "nodes": c, "valu": p, "fit": float(setup + per_node * c)}
             for c, p, v0, x0 in fb]
+    for key, tp in tms.items():
+        A = np.array([[1.0, t, st] for t, st, _, _, _ in tp])
+        y = np.array([p for _, _, p, _, _ in tp])
+        (setup, per_term, per_step), *_ = np.linalg.lstsq(A, y, rcond=None)
+        model[key]["temme_setup"] = float(setup)
+        model[key]["temme_per_term"] = float(per_term)
+        model[key]["temme_per_step"] = float(per_step)
+        model[key]["temme_probes"] = [
+            {"v": v0, "x": x0, "terms": t, "steps": st, "valu": p,
+             "fit": float(setup + per_term * t + per_step * st)} for t, st, p, v0, x0 in tp]
     with open(OUT, "w") as f:
         json.dump(model, f, indent=1)
     return model

@@ -1,8 +1,10 @@
-"""The K fallback's cosh-integral rule at its own internal boundaries, against
-the binary128 oracle: the switch between a window that starts at t = 0 and
-an interior window (including walks that step past t = 0 and use the mirror
-node of the even integrand), the x = 1e-10 switch to the small-argument
-forms, orders near zero, and the node counts the op model relies on."""
+"""The K fallback at its own internal boundaries, against the binary128
+oracle: the cosh-integral rule's switch between a window that starts at
+t = 0 and an interior window (including walks that step past t = 0 and use
+the mirror node of the even integrand), the binary64 Temme series at
+x <= 1.25 (its bound, mu = v - rint(v) near 0 and +-1/2, every order step),
+the x = 1e-10 switch to the small-argument forms, orders near zero, and the
+node and term counts the op model relies on."""
 import numpy as np
 import pytest
 import torch
@@ -50,7 +52,7 @@ def lb():
     return m
 
 
-def _check(lb, oracle, v, x, dtype=torch.float64):
+def _check(lb, oracle, v, x, dtype=torch.float64, variant=None):
     v = np.asarray(v, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     if dtype == torch.float32:
@@ -58,7 +60,10 @@ def _check(lb, oracle, v, x, dtype=torch.float64):
         x = x.astype(np.float32).astype(np.float64)
     dv = torch.from_numpy(v).to("cuda:0", dtype)
     dx = torch.from_numpy(x).to("cuda:0", dtype)
-    y = lb.log_kv(dv, dx).double().cpu().numpy()
+    if variant is None:
+        y = lb.log_kv(dv, dx).double().cpu().numpy()
+    else:
+        y = lb.eval_variant("K", variant, "grouped", dv, dx).cpu().numpy()
     hi, lo = oracle.log_kv(v, x)
     assert np.array_equal(np.isfinite(y), np.isfinite(hi))
     e = cond_err(y, hi, lo, v, x)
@@ -66,12 +71,15 @@ def _check(lb, oracle, v, x, dtype=torch.float64):
 
 
 def test_walks_past_zero(lb, oracle):
+    """The binary64 default path takes these (small-x) points through Temme's
+    series; the Table 1 variant keeps the cosh rule there."""
     v, x = np.array(MIRROR).T
-    e = _check(lb, oracle, v, x)
-    assert e.max() <= TOL64, e.max()
-    # the same points perturbed: both sides of the window switch
-    for s in (1 - 1e-3, 1 + 1e-3, 0.97, 1.03):
-        assert _check(lb, oracle, v, x * s).max() <= TOL64
+    for variant in ("paper_regimes", None):
+        e = _check(lb, oracle, v, x, variant=variant)
+        assert e.max() <= TOL64, (variant, e.max())
+        # the same points perturbed: both sides of the window switch
+        for s in (1 - 1e-3, 1 + 1e-3, 0.97, 1.03):
+            assert _check(lb, oracle, v, x * s, variant=variant).max() <= TOL64
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -116,16 +124,56 @@ def test_fallback_region_grid(lb, oracle):
     v, x = np.meshgrid(vs, xs)
     e = _check(lb, oracle, v.ravel(), x.ravel())
     assert e.max() <= TOL64, e.max()
-    n = lb.k_nodes(torch.from_numpy(v.ravel()).cuda(), torch.from_numpy(x.ravel()).cuda())
-    n = n.cpu().numpy()
-    integral = v.ravel() != 0.0          # order 0 runs its expansions, no nodes
+    dv, dx = torch.from_numpy(v.ravel()).cuda(), torch.from_numpy(x.ravel()).cuda()
+    n = lb.k_nodes(dv, dx).cpu().numpy()
+    k = lb.k_terms(dv, dx).cpu().numpy()
+    # order 0 runs its expansions; other orders Temme's series up to x = 1.25
+    # and the integral above
+    series = (v.ravel() != 0.0) & (x.ravel() <= 1.25)
+    integral = (v.ravel() != 0.0) & (x.ravel() > 1.25)
     assert n[integral].min() > 0 and n.max() < 400 and not n[~integral].any()
+    assert k[series].min() >= 1 and k.max() <= 20 and not k[~series].any()
 
 
 def test_node_counts_on_the_stress_grid(lb):
     from paper_2409_08729_amd import workloads as wl
     v, x = wl.m3(1 << 20)
-    n = lb.k_nodes(torch.from_numpy(v).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    dv, dx = torch.from_numpy(v).cuda(), torch.from_numpy(x).cuda()
+    n = lb.k_nodes(dv, dx).cpu().numpy()
+    k = lb.k_terms(dv, dx).cpu().numpy()
     fb = n > 0
-    assert 0.3 < fb.mean() < 0.5
-    assert 20 < n[fb].mean() < 60 and n.max() < 400, (n[fb].mean(), n.max())
+    tm = k > 0
+    assert not (fb & tm).any()
+    # ~39% of the grid is in the fallback region, ~78% of it at x <= 1.25
+    assert 0.05 < fb.mean() < 0.15 and 0.25 < tm.mean() < 0.40, (fb.mean(), tm.mean())
+    assert 10 < n[fb].mean() < 40 and n.max() < 400, (n[fb].mean(), n.max())
+    assert 2 < k[tm].mean() < 8 and k.max() <= 20, (k[tm].mean(), k.max())
+    assert x[tm].max() <= 1.25 and x[fb].min() > 1.25
+
+
+def test_temme_region(lb, oracle):
+    """Temme's series over its whole region: x log-spaced from the
+    small-argument switch to its bound 1.25 (and one ulp either side of
+    both), orders whose fractional part mu = v - rint(v) sits at 0 +- 1e-12,
+    +-1e-6, +-1/4 and +-1/2 (rint rounds halves to even), for every order
+    step 0..14, against the oracle."""
+    xs = np.concatenate([10 ** np.linspace(-10, np.log10(1.25), 60),
+                         [1e-10, np.nextafter(1e-10, 1), np.nextafter(1.25, 0), 1.25,
+                          np.nextafter(1.25, 2)]])
+    base = np.arange(0.0, 15.0)
+    off = np.array([1e-12, -1e-12, 1e-6, -1e-6, 0.25, -0.25, 0.5, -0.4999999, 0.123])
+    vs = (base[:, None] + off[None, :]).ravel()
+    vs = vs[(vs > 0) & (vs <= 14.5)]
+    v, x = np.meshgrid(vs, xs)
+    e = _check(lb, oracle, v.ravel(), x.ravel())
+    i = int(np.argmax(e))
+    assert e.max() <= TOL64, (e.max(), v.ravel()[i], x.ravel()[i])
+
+
+def test_temme_random(lb, oracle):
+    g = np.random.default_rng(41)
+    v = g.uniform(0.0, 14.5, 6000)
+    x = np.concatenate([10 ** g.uniform(-10, np.log10(1.25), 3000), g.uniform(0.0, 1.25, 3000)])
+    x = np.maximum(x, 1e-10)
+    e = _check(lb, oracle, v, x)
+    assert e.max() <= TOL64, e.max()

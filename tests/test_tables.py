@@ -245,3 +245,72 @@ def test_lgamma1p_table():
         ref = math.lgamma(1.0 + float(v))
         worst32 = max(worst32, abs(float(acc) - ref) / max(1.0, abs(ref)))
     assert worst32 < 1e-6, worst32
+
+
+def _header_row_array(text: str, name: str) -> list[list[float]]:
+    import re
+    m = re.search(name + r"\[(\d+)\]\[(\d+)\] = \{(.*?)\n\};", text, re.S)
+    assert m, name
+    return [[float.fromhex(t.strip()) for t in row.split(",") if t.strip()]
+            for row in re.findall(r"\{([^{}]*)\}", m.group(3))]
+
+
+def _header_flat(text: str, name: str) -> list[float]:
+    import re
+    m = re.search(name + r"\[\d+\] = \{([^}]*)\};", text)
+    assert m, name
+    return [float.fromhex(t.strip()) if t.strip() != "0" else 0.0 for t in m.group(1).split(",")]
+
+
+def _horner(c, t):
+    s = c[-1]
+    for a in reversed(c[:-1]):
+        s = s * t + a
+    return s
+
+
+def test_temme_gamma_polynomials():
+    """G1, G2 of Temme's series as binary64 polynomials in t = mu^2: at mu = 0
+    G1 = -gamma (Euler's constant) and G2 = 1; across |mu| <= 1/2 the
+    reciprocals of G2 -+ mu G1 are Gamma(1 +- mu) to the C library's
+    accuracy, and G1 agrees with the difference quotient of 1/Gamma computed
+    in 60-digit decimals away from mu = 0."""
+    text = gt.render_header()
+    g1, g2 = _header_row_array(text, "kTmG64")
+    assert len(g1) == len(g2) == gt.TM_G_DEG + 1
+    assert abs(g1[0] + 0.5772156649015329) <= 1.2e-16 and abs(g2[0] - 1.0) <= 2.3e-16
+    worst = 0.0
+    for mu in np.linspace(-0.5, 0.5, 401):
+        t = mu * mu
+        a, b = _horner(g1, t), _horner(g2, t)
+        for sgn in (1.0, -1.0):
+            ref = math.gamma(1.0 + sgn * mu)
+            got = 1.0 / (b - sgn * mu * a)
+            worst = max(worst, abs(got - ref) / ref)
+    assert worst < 6e-16, worst
+    from decimal import Decimal
+    for mu in (0.013, 0.1, 0.37, 0.5):
+        e1, e2 = gt.temme_g(Decimal(mu) ** 2)
+        t = mu * mu
+        assert abs(_horner(g1, t) - float(e1)) <= 2e-16 * abs(float(e1)), mu
+        assert abs(_horner(g2, t) - float(e2)) <= 2e-16 * abs(float(e2)), mu
+
+
+def test_temme_sinc_and_sinh_series():
+    """sin(pi mu)/(pi mu) as a polynomial in mu^2 against the C library's sin
+    on |mu| <= 1/2 (1 at 0, 2/pi at 1/2); sinh(s)/s against sinh on |s| < 1;
+    the 1/k table exact."""
+    text = gt.render_header()
+    sc = _header_flat(text, "kTmSinc64")
+    sh = _header_flat(text, "kTmSinh64")
+    ik = _header_flat(text, "kTmInvK64")
+    assert len(sc) == gt.TM_SINC_TERMS and len(sh) == gt.TM_SINH_TERMS
+    assert sc[0] == 1.0 and abs(_horner(sc, 0.25) - 2 / math.pi) < 2.3e-16
+    for mu in np.linspace(1e-3, 0.5, 300):
+        ref = math.sin(math.pi * mu) / (math.pi * mu)
+        assert abs(_horner(sc, mu * mu) - ref) < 3e-16, mu
+    for s_ in np.linspace(1e-3, 1.0, 300):
+        ref = math.sinh(s_) / s_
+        assert abs(_horner(sh, s_ * s_) - ref) < 6e-16 * ref, s_   # ref: sinh and a division
+    assert ik[0] == 0.0 and all(ik[k] == 1.0 / k for k in range(1, len(ik)))
+    assert len(ik) == gt.TM_MAX_TERMS + 1
