@@ -144,14 +144,13 @@ def op_counts(lb, torch, sets):
                     n_of = va[m & sm].to(torch.int64)
                     mix[(j, kind)][side] = torch.bincount(
                         n_of, minlength=K_INT_ORDER_MAX + 1).cpu().tolist()
-                if v.dtype == torch.float64:
-                    # Temme-series elements: term counts and order steps
-                    tt = lb.k_terms(v, x).to(torch.int64)
-                    tm = tt > 0
-                    steps = (torch.round(va[tm]) - 1).clamp(min=0)
-                    mix[(j, kind)]["temme"] = int(tm.sum().item())
-                    mix[(j, kind)]["temme_terms"] = int(tt.sum().item())
-                    mix[(j, kind)]["temme_steps"] = int(steps.sum().item())
+                # Temme-series elements: term counts and order steps
+                tt = lb.k_terms(v, x).to(torch.int64)
+                tm = tt > 0
+                steps = (torch.round(va[tm]) - 1).clamp(min=0)
+                mix[(j, kind)]["temme"] = int(tm.sum().item())
+                mix[(j, kind)]["temme_terms"] = int(tt.sum().item())
+                mix[(j, kind)]["temme_steps"] = int(steps.sum().item())
         nodes[j] = int(lb.k_nodes(v, x).to(torch.int64).sum().item())
     return mix, nodes
 

@@ -80,10 +80,10 @@ int lbessel_log_iv_f32(const float *v, const float *x, float *out,
  * paper's fallback of Algorithm 1), for x >= 1e-10: integer orders 0..14
  * take the integer-order path of lbessel_log_kv_order_f64 (the order-0/1
  * expansions, then the recurrence K_{j+1} = K_{j-1} + (2j/x) K_j); other
- * orders, in binary64 at x <= 1.25, Temme's series for K_mu and K_{mu+1} at
- * the fractional part mu = v - rint(v) followed by the same recurrence up to
- * v (N. M. Temme, J. Comput. Phys. 19, 1975); otherwise (binary64 above
- * x = 1.25, every binary32 case) the trapezoid rule on
+ * orders at x <= 1.25 Temme's series for K_mu and K_{mu+1} at the
+ * fractional part mu = v - rint(v) followed by the same recurrence up to v
+ * (N. M. Temme, J. Comput. Phys. 19, 1975); above x = 1.25 the trapezoid
+ * rule on
  * K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9), summed in
  * log scale over the nodes within a fixed drop of the integrand's peak.  For
  * x < 1e-10 the two leading terms of K_v = pi (I_{-v} - I_v) / (2 sin v pi)
@@ -321,21 +321,22 @@ int lbessel_classify(int kind, int precision, const void *v, const void *x,
  * Integrand evaluations the log K fallback spends on each element (for the
  * op model of the benchmark): the node count of its integral rule, 0 for
  * elements of another branch or sub-case (integer orders 0..14, x < 1e-10
- * and, in binary64, the Temme series at x <= 1.25 run no integral).
+ * and the Temme series at x <= 1.25 run no integral).
  * precision 64 or 32.
  */
 int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
                     int64_t n, void *stream);
 
 /*
- * Series terms the binary64 log K fallback's Temme branch (1e-10 <= x <= 1.25,
+ * Series terms the log K fallback's Temme branch (1e-10 <= x <= 1.25,
  * non-integer order) spends on each element, after its first term; 0 for
  * elements of another branch or sub-case (for the op model of the
- * benchmark, beside lbessel_k_nodes).  Device arrays of n elements; n = 0 is
- * a no-op; LBESSEL_EINVAL for null pointers or n < 0.
+ * benchmark, beside lbessel_k_nodes).  precision 64 or 32 (v and x read as
+ * double or float); device arrays of n elements; n = 0 is a no-op;
+ * LBESSEL_EINVAL for another precision, null pointers or n < 0.
  */
-int lbessel_k_terms(const double *v, const double *x, int32_t *terms, int64_t n,
-                    void *stream);
+int lbessel_k_terms(int precision, const void *v, const void *x, int32_t *terms,
+                    int64_t n, void *stream);
 
 /*
  * The library's binary64 elementary functions on the device, for testing

@@ -64,7 +64,7 @@ def _load():
         "lbessel_vmf_log_norm_grad_f64": [vp, ctypes.c_double, vp, i64, vp],
         "lbessel_classify": [ctypes.c_int, ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_k_nodes": [ctypes.c_int, vp, vp, vp, i64, vp],
-        "lbessel_k_terms": [vp, vp, vp, i64, vp],
+        "lbessel_k_terms": [ctypes.c_int, vp, vp, vp, i64, vp],
         "lbessel_elementary_f64": [ctypes.c_int, vp, vp, i64, vp],
         "lbessel_log_iv_order_f64": [ctypes.c_double, vp, vp, i64, vp],
         "lbessel_log_kv_order_f64": [ctypes.c_double, vp, vp, i64, vp],
@@ -414,15 +414,14 @@ def elementary(op: str, a: torch.Tensor) -> torch.Tensor:
 
 
 def k_terms(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-    """Temme-series terms of the float64 log K fallback per element (int32; 0
-    for elements that take another branch or sub-case)."""
+    """Temme-series terms of the log K fallback per element (int32; 0 for
+    elements that take another branch or sub-case)."""
     v, x = _prep(v, x)
-    if x.dtype != torch.float64:
-        raise LbesselError("k_terms takes float64 tensors")
     out = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    prec = 64 if x.dtype == torch.float64 else 32
     with torch.cuda.device(x.device):
-        _check(_load().lbessel_k_terms(v.data_ptr(), x.data_ptr(), out.data_ptr(), x.numel(),
-                                       _stream(x)), "lbessel_k_terms")
+        _check(_load().lbessel_k_terms(prec, v.data_ptr(), x.data_ptr(), out.data_ptr(),
+                                       x.numel(), _stream(x)), "lbessel_k_terms")
     return out
 
 

@@ -10,8 +10,8 @@
 //           terms fall below the working precision (text after eq. K);
 //   K fallback (the library's path): for x >= 1e-10 integer orders 0..14
 //           by the order-0/1 expansions and the order recurrence
-//           (order_int_fb); other orders in binary64 at x <= 1.25 by
-//           Temme's series and the same recurrence (br_k_temme); otherwise
+//           (order_int_fb); other orders at x <= 1.25 by Temme's series
+//           and the same recurrence (br_k_temme); otherwise
 //           the trapezoid rule on
 //           K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt (DLMF 10.32.9)
 //           over the nodes within a fixed drop of the log-integrand's peak
@@ -903,7 +903,7 @@ __device__ __forceinline__ int i_cost_bucket(T x) {
 // for an interior window (the peak estimate stands more than 40 above the
 // integrand at t = 0), whose right and left walks would otherwise run one
 // after the other in chunks shared with the single walk of windows that
-// start at 0.  With TEMME (the binary64 default path) buckets 0..3 hold the
+// start at 0.  With TEMME (the default variant) buckets 0..3 hold the
 // Temme-series elements (x <= 1.25) by term and order-step estimate, and
 // the integer orders; 4, 5 and 6 the integral's.  Only used to order work
 // inside a tile; any value is correct.
@@ -1103,9 +1103,9 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
 }
 
 // ---------------------------------------------------------------------------
-// K fallback for small arguments (binary64): Temme's series
+// K fallback for small arguments: Temme's series
 // ---------------------------------------------------------------------------
-// For 1e-10 <= x <= kTemmeX = 1.25 and a non-integer order v the binary64 log K
+// For 1e-10 <= x <= kTemmeX = 1.25 and a non-integer order v the log K
 // fallback takes K_mu and K_{mu+1} at the fractional part mu = v - n,
 // n = rint(v), |mu| <= 1/2, from Temme's series (N. M. Temme, J. Comput.
 // Phys. 19, 1975), with q = x^2/4, c_k = q^k / k!, s = mu ln(2/x):
@@ -1126,56 +1126,73 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
 // Cost ~150 + ~20 per term (2..11 terms) + ~8 per order step, against
 // ~290 + ~38 per node (20..70 nodes there) for the integral; the series is
 // independent of the integral representations (the paper's and DLMF 10.32.9).
-// nterms, if given, receives the number of series terms after f_0.
-__device__ __forceinline__ double br_k_temme(double v, double x, int *nterms = nullptr) {
-    const double n = rint(v);
-    const double mu = v - n;
-    const double t = mu * mu;
-    const double L = Cst<double>::ln2 - llog(x);             // ln(2/x) > 0
-    const double s = mu * L;
-    const double e = lexp_b(s);                               // (2/x)^mu
-    const double ie = lrcp(e);
-    const LB_CONST_AS double *G = opaque_const<double>(&tables::kTmG64[0][0]);
-    const double g1 = horner<double, tables::kTmGCoefs>(G, t);
-    const double g2 = horner<double, tables::kTmGCoefs>(G + tables::kTmGCoefs, t);
-    const double sinc = horner<double, tables::kTmSincTerms>(
-        opaque_const<double>(tables::kTmSinc64), t);
-    double shs;                                               // sinh(s)/s
-    if (fabs(s) < 1.0)
-        shs = horner<double, tables::kTmSinhTerms>(opaque_const<double>(tables::kTmSinh64), s * s);
+// Binary32: the same with binary32 tables and stop rule (2^-27), the order
+// recurrence in binary64.  nterms, if given, receives the number of series
+// terms after f_0.
+template <typename T> struct TabTm;
+template <> struct TabTm<double> {
+    static __device__ __forceinline__ const double *g() { return &tables::kTmG64[0][0]; }
+    static __device__ __forceinline__ const double *sinc() { return tables::kTmSinc64; }
+    static __device__ __forceinline__ const double *sinh() { return tables::kTmSinh64; }
+    static __device__ __forceinline__ const double *invk() { return tables::kTmInvK64; }
+};
+template <> struct TabTm<float> {
+    static __device__ __forceinline__ const float *g() { return &tables::kTmG32[0][0]; }
+    static __device__ __forceinline__ const float *sinc() { return tables::kTmSinc32; }
+    static __device__ __forceinline__ const float *sinh() { return tables::kTmSinh32; }
+    static __device__ __forceinline__ const float *invk() { return tables::kTmInvK32; }
+};
+
+template <typename T>
+__device__ __forceinline__ T br_k_temme(T v, T x, int *nterms = nullptr) {
+    const T n = rint(v);
+    const T mu = v - n;
+    const T t = mu * mu;
+    const T L = Cst<T>::ln2 - llog(x);                        // ln(2/x) > 0
+    const T s = mu * L;
+    const T e = lexp_b(s);                                    // (2/x)^mu
+    const T ie = lrcp(e);
+    const LB_CONST_AS T *G = opaque_const<T>(TabTm<T>::g());
+    const T g1 = horner<T, tables::kTmGCoefs>(G, t);
+    const T g2 = horner<T, tables::kTmGCoefs>(G + tables::kTmGCoefs, t);
+    const T sinc = horner<T, tables::kTmSincTerms>(opaque_const<T>(TabTm<T>::sinc()), t);
+    T shs;                                                    // sinh(s)/s
+    if (fabs(s) < T(1))
+        shs = horner<T, tables::kTmSinhTerms>(opaque_const<T>(TabTm<T>::sinh()), s * s);
     else
-        shs = (e - ie) * (0.5 * lrcp(s));
-    const double ch = 0.5 * (e + ie);
-    double f = fma(g1, ch, shs * L * g2) * lrcp(sinc);
-    double p = 0.5 * e * lrcp(fma(-mu, g1, g2));               // 1/Gamma(1+mu) = G2 - mu G1
-    double q = 0.5 * ie * lrcp(fma(mu, g1, g2));               // 1/Gamma(1-mu) = G2 + mu G1
-    const double qx = 0.25 * x * x;
-    const LB_CONST_AS double *ik = opaque_const<double>(tables::kTmInvK64);
-    double c = 1.0, s0 = f, s1 = p, kk = 0.0;
+        shs = (e - ie) * (T(0.5) * lrcp(s));
+    const T ch = T(0.5) * (e + ie);
+    T f = fma(g1, ch, shs * L * g2) * lrcp(sinc);
+    T p = T(0.5) * e * lrcp(fma(-mu, g1, g2));                // 1/Gamma(1+mu) = G2 - mu G1
+    T q = T(0.5) * ie * lrcp(fma(mu, g1, g2));                // 1/Gamma(1-mu) = G2 + mu G1
+    const T qx = T(0.25) * x * x;
+    const LB_CONST_AS T *ik = opaque_const<T>(TabTm<T>::invk());
+    T c = T(1), s0 = f, s1 = p, kk = T(0);
     int k = 0;
     while (k < tables::kTmMaxTerms) {
         ++k;
-        kk += 1.0;
-        const double d = lrcp(fma(kk, kk, -t));
+        kk += T(1);
+        const T d = lrcp(fma(kk, kk, -t));
         f = fma(kk, f, p + q) * d;
         c = c * qx * ik[k];
         p = p * (kk + mu) * d;
         q = q * (kk - mu) * d;
         s0 = fma(c, f, s0);
         s1 = fma(c, fma(-kk, f, p), s1);
-        const double eps = Cst<double>::series_eps;
+        const T eps = Cst<T>::series_eps;
         if (c * fabs(f) <= eps * s0 && c * fma(kk, fabs(f), fabs(p)) <= eps * s1)
             break;
     }
     if (nterms != nullptr)
         *nterms = k;
-    if (n == 0.0)
+    if (n == T(0))
         return llog(s0);
-    const double k1 = s1 * (2.0 * lrcp(x));                  // K_{mu+1}
-    const double l1 = llog(k1);
-    if (n == 1.0)
+    const T k1 = s1 * (T(2) * lrcp(x));                       // K_{mu+1}
+    const T l1 = llog(k1);
+    if (n == T(1))
         return l1;
-    return l1 + llog(k_up_ratio(s0 * lrcp(k1), mu, int(n), x));
+    return l1 + T(llog(k_up_ratio(double(s0) * lrcp(double(k1)), double(mu), int(n),
+                                  double(x))));
 }
 
 template <typename T, int KIND>
@@ -1234,13 +1251,12 @@ __device__ __forceinline__ T eval_branch(int b, T v, T x, const FbTab<KIND, T> *
     if (!u_integral && x >= T(1e-10)) {
         if (VAR == VAR_DEFAULT && int_order(v))
             return order_int_fb<T, KIND_K>(int(v), x);
-        if constexpr (std::is_same<T, float>::value) {
+        if (VAR == VAR_DEFAULT && x <= T(tables::kTemmeX))
+            return br_k_temme<T>(v, x);
+        if constexpr (std::is_same<T, float>::value)
             return br_k_cosh32(v, x, kt);
-        } else {
-            if (VAR == VAR_DEFAULT && x <= tables::kTemmeX)
-                return br_k_temme(v, x);
+        else
             return br_k_cosh(v, x, kt);
-        }
     }
     if (x < T(1e-10) && v < T(0.3))
         return T(br_k_tiny_x(double(v), double(x)));

@@ -324,8 +324,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
                 else
                     b0 = C::f0 + ((C::fb == 1) ? 0
                                   : (KIND == KIND_K)
-                                      ? k_cost_bucket<kKBuckets, (std::is_same<T, double>::value &&
-                                                                  VAR == VAR_DEFAULT)>(double(v), double(x))
+                                      ? k_cost_bucket<kKBuckets, VAR == VAR_DEFAULT>(double(v),
+                                                                                     double(x))
                                                      : i_cost_bucket<kIBuckets>(x));
             } else {
                 T ys;
@@ -672,8 +672,8 @@ __global__ __launch_bounds__(kThreads) void k_classify(const T *v, const T *x, u
 
 // Integrand evaluations of the K fallback per element: the node count of the
 // cosh-integral rule; 0 for every other branch, special value or sub-case
-// (integer orders, x < 1e-10 and, in binary64, the Temme series at
-// x <= 1.25 run no integral).
+// (integer orders, x < 1e-10 and the Temme series at x <= 1.25 run no
+// integral).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int32_t *nodes,
                                                      int64_t n) {
@@ -687,9 +687,11 @@ __global__ __launch_bounds__(kThreads) void k_knodes(const T *v, const T *x, int
     // integer orders and x < 1e-10 take closed expansions, no integral
     if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB &&
         xx >= T(1e-10) && !int_order(vv)) {
-        if constexpr (std::is_same<T, float>::value)
+        if (xx <= T(tables::kTemmeX))
+            c = 0;
+        else if constexpr (std::is_same<T, float>::value)
             br_k_cosh32(vv, xx, kt, &c);
-        else if (xx > tables::kTemmeX)
+        else
             br_k_cosh(vv, xx, kt, &c);
     }
     nodes[i] = c;
@@ -707,19 +709,20 @@ __global__ __launch_bounds__(kThreads) void k_elementary(int op, const double *a
              : (op == 3) ? llog(x) : llog1p(x);
 }
 
-// Series terms of the binary64 K fallback's Temme branch per element (after
-// f_0); 0 for every other branch, special value or sub-case.
-__global__ __launch_bounds__(kThreads) void k_kterms(const double *v, const double *x,
-                                                     int32_t *terms, int64_t n) {
+// Series terms of the K fallback's Temme branch per element (after f_0); 0
+// for every other branch, special value or sub-case.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kterms(const T *v, const T *x, int32_t *terms,
+                                                     int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n)
         return;
-    const double vv = fabs(v[i]), xx = x[i];
-    double y;
+    const T vv = fabs(v[i]), xx = x[i];
+    T y;
     int c = 0;
-    if (!special_value<double, KIND_K>(vv, xx, &y) && classify<double, KIND_K>(vv, xx) == BR_FB &&
-        xx >= 1e-10 && xx <= tables::kTemmeX && !int_order(vv))
-        br_k_temme(vv, xx, &c);
+    if (!special_value<T, KIND_K>(vv, xx, &y) && classify<T, KIND_K>(vv, xx) == BR_FB &&
+        xx >= T(1e-10) && xx <= T(tables::kTemmeX) && !int_order(vv))
+        br_k_temme<T>(vv, xx, &c);
     terms[i] = c;
 }
 
@@ -1140,8 +1143,9 @@ int lbessel_elementary_f64(int op, const double *a, double *out, int64_t n, void
     return launch_status();
 }
 
-int lbessel_k_terms(const double *v, const double *x, int32_t *terms, int64_t n, void *s) {
-    if (n < 0)
+int lbessel_k_terms(int precision, const void *v, const void *x, int32_t *terms, int64_t n,
+                    void *s) {
+    if (n < 0 || (precision != 64 && precision != 32))
         return LBESSEL_EINVAL;
     if (n == 0)
         return LBESSEL_OK;
@@ -1150,8 +1154,13 @@ int lbessel_k_terms(const double *v, const double *x, int32_t *terms, int64_t n,
     uint32_t blocks;
     if (!grid_ok(n, kThreads, &blocks))
         return LBESSEL_EINVAL;
-    hipLaunchKernelGGL(k_kterms, dim3(blocks), dim3(kThreads), 0, static_cast<hipStream_t>(s),
-                       v, x, terms, n);
+    hipStream_t st = static_cast<hipStream_t>(s);
+    if (precision == 64)
+        hipLaunchKernelGGL(k_kterms<double>, dim3(blocks), dim3(kThreads), 0, st,
+                           (const double *)v, (const double *)x, terms, n);
+    else
+        hipLaunchKernelGGL(k_kterms<float>, dim3(blocks), dim3(kThreads), 0, st,
+                           (const float *)v, (const float *)x, terms, n);
     return launch_status();
 }
 

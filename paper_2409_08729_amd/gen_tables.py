@@ -623,7 +623,8 @@ def render_header() -> str:
         lines.append("    {" + ", ".join(f64_hex(dec_to_f64(c)) for c in lgamma1p_poly(j)) + "},")
     lines.append("};")
     lines.append("// Temme's series (K fallback, x <= kTemmeX): G1, G2 as polynomials in t = mu^2")
-    lines.append("// (index = power), sin(pi mu)/(pi mu) in t, sinh(s)/s in s^2.")
+    lines.append("// (index = power), sin(pi mu)/(pi mu) in t, sinh(s)/s in s^2, 1/k; binary64")
+    lines.append("// and binary32 copies.")
     lines.append(f"constexpr double kTemmeX = {f64_hex(to_f64(TM_X))};")
     lines.append(f"constexpr int kTmGCoefs = {TM_G_DEG + 1};")
     lines.append(f"constexpr int kTmSincTerms = {TM_SINC_TERMS};")
@@ -641,6 +642,19 @@ def render_header() -> str:
                  + "};")
     lines.append(f"__constant__ const double kTmSinh64[{TM_SINH_TERMS}] = {{"
                  + ", ".join(f64_hex(to_f64(Fraction(1, math.factorial(2 * k + 1))))
+                             for k in range(TM_SINH_TERMS)) + "};")
+    lines.append(f"__constant__ const float kTmG32[2][{TM_G_DEG + 1}] = {{")
+    for which in (0, 1):
+        lines.append("    {" + ", ".join(f32_hex(dec_to_f32(c)) for c in temme_g_poly(which))
+                     + "},")
+    lines.append("};")
+    lines.append(f"__constant__ const float kTmSinc32[{TM_SINC_TERMS}] = {{"
+                 + ", ".join(f32_hex(dec_to_f32(c)) for c in temme_sinc_series()) + "};")
+    lines.append(f"__constant__ const float kTmInvK32[{TM_MAX_TERMS + 1}] = {{0, "
+                 + ", ".join(f32_hex(to_f32_exact(Fraction(1, k)))
+                             for k in range(1, TM_MAX_TERMS + 1)) + "};")
+    lines.append(f"__constant__ const float kTmSinh32[{TM_SINH_TERMS}] = {{"
+                 + ", ".join(f32_hex(to_f32_exact(Fraction(1, math.factorial(2 * k + 1))))
                              for k in range(TM_SINH_TERMS)) + "};")
     lines.append(f"constexpr double kEulerGamma64 = {f64_hex(dec_to_f64(Decimal(EULER_GAMMA_50)))};")
     lines.append(f"constexpr float kEulerGamma32 = {f32_hex(dec_to_f32(Decimal(EULER_GAMMA_50)))};")

@@ -14,7 +14,7 @@ each K fallback point (lbessel_k_nodes) to the JSON file.  The set "quad"
 probes the paper's own 600-node integral (the u_integral variant); the set
 "int" the integer-order path of the K fallback (orders 0..14, one point with
 x <= 2 and one above, where the order-0/1 expansions switch form); the set
-"temme" the binary64 K fallback's Temme series (x <= 1.25), whose cost is
+"temme" the K fallback's Temme series (x <= 1.25), whose cost is
 fitted as setup + per_term x terms + per_step x order steps (terms from
 lbessel_k_terms, steps = max(rint(v) - 1, 0)).
 
@@ -38,8 +38,8 @@ import sys
 
 # (precision, kind, branch, v, x): well inside each branch's region; the Debye
 # branch at one order per term-count tier (U_13, U_9, U_6, U_4); the K
-# fallback at points with different node counts (non-integer orders: integer
-# orders up to 14 take the integer-order path, and binary64 x <= 1.25 the
+# fallback at points with different node counts (non-integer orders, x > 1.25:
+# integer orders up to 14 take the integer-order path and x <= 1.25 the
 # Temme series, both probed apart).
 _FB_K64 = [(3.3, 5.0), (0.5, 1.5), (12.3, 1.3), (1.1, 2.5), (6.2, 2.0), (0.1, 3.0),
            (13.7, 10.0), (2.2, 15.0), (9.5, 1.4), (14.4, 4.0)]
@@ -47,7 +47,10 @@ _FB_K64 = [(3.3, 5.0), (0.5, 1.5), (12.3, 1.3), (1.1, 2.5), (6.2, 2.0), (0.1, 3.
 _TM_K64 = [(0.3, 1e-4), (0.3, 0.01), (0.3, 0.3), (0.3, 1.2), (4.4, 1e-3), (4.4, 0.1),
            (4.4, 1.0), (9.7, 1e-4), (9.7, 0.05), (9.7, 1.2), (14.3, 1e-3), (14.3, 0.5),
            (1.6, 0.02), (7.2, 0.7)]
-_FB_K32 = [(3.3, 5.0), (0.5, 1e-4), (8.1, 0.01), (1.1, 1.0), (6.2, 2.0), (0.1, 0.01),
+# binary32: orders up to 9 (the binary32 fallback region)
+_TM_K32 = [(0.3, 1e-4), (0.3, 0.01), (0.3, 0.3), (0.3, 1.2), (4.4, 1e-3), (4.4, 0.1),
+           (4.4, 1.0), (8.7, 1e-4), (8.7, 0.05), (8.7, 1.2), (1.6, 0.02), (7.2, 0.7)]
+_FB_K32 = [(3.3, 5.0), (0.5, 1.5), (8.1, 1.3), (1.1, 2.5), (6.2, 2.0), (0.1, 3.0),
            (8.5, 5.0), (2.2, 6.5)]
 # integer orders of the K fallback region: 0..14 in binary64, 0..9 in binary32
 # (above 9 the binary32 classifier takes the Debye branch at every x)
@@ -69,7 +72,8 @@ SETS = {
     "quad": [(64, "K", "u_integral", 3.0, 5.0), (64, "K", "u_integral", 0.5, 1e-4)],
     "int": [(p, "K", 2, float(n), x) for p in (64, 32) for x in INT_X
             for n in range(INT_MAX[p] + 1)],
-    "temme": [(64, "K", 2, v, x) for v, x in _TM_K64],
+    "temme": [(64, "K", 2, v, x) for v, x in _TM_K64]
+             + [(32, "K", 2, v, x) for v, x in _TM_K32],
 }
 U_TIER_NAMES = {20.0: "u13", 40.0: "u9", 100.0: "u6", 400.0: "u4"}
 NAMES = {0: "mu20", 2: "fallback"}
@@ -92,8 +96,7 @@ def probe(points_json: str, sets: list[str], n: int = 1 << 18) -> None:
                 lb.eval_branch(kind, b, v, x)
             torch.cuda.synchronize()
             c = int(lb.k_nodes(v[:1], x[:1]).item()) if (kind, b) == ("K", 2) else 0
-            tm = (int(lb.k_terms(v[:1], x[:1]).item())
-                  if (kind, b) == ("K", 2) and prec == 64 else 0)
+            tm = int(lb.k_terms(v[:1], x[:1]).item()) if (kind, b) == ("K", 2) else 0
             pts.append([name, prec, kind, b, v0, x0])
             nodes.append(c)
             terms.append(tm)

@@ -151,7 +151,8 @@ def test_node_counts_on_the_stress_grid(lb):
     assert x[tm].max() <= 1.25 and x[fb].min() > 1.25
 
 
-def test_temme_region(lb, oracle):
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_temme_region(lb, oracle, dtype):
     """Temme's series over its whole region: x log-spaced from the
     small-argument switch to its bound 1.25 (and one ulp either side of
     both), orders whose fractional part mu = v - rint(v) sits at 0 +- 1e-12,
@@ -165,15 +166,32 @@ def test_temme_region(lb, oracle):
     vs = (base[:, None] + off[None, :]).ravel()
     vs = vs[(vs > 0) & (vs <= 14.5)]
     v, x = np.meshgrid(vs, xs)
-    e = _check(lb, oracle, v.ravel(), x.ravel())
+    e = _check(lb, oracle, v.ravel(), x.ravel(), dtype)
     i = int(np.argmax(e))
-    assert e.max() <= TOL64, (e.max(), v.ravel()[i], x.ravel()[i])
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert e.max() <= tol, (e.max(), v.ravel()[i], x.ravel()[i])
 
 
-def test_temme_random(lb, oracle):
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_temme_random(lb, oracle, dtype):
     g = np.random.default_rng(41)
     v = g.uniform(0.0, 14.5, 6000)
     x = np.concatenate([10 ** g.uniform(-10, np.log10(1.25), 3000), g.uniform(0.0, 1.25, 3000)])
     x = np.maximum(x, 1e-10)
-    e = _check(lb, oracle, v, x)
-    assert e.max() <= TOL64, e.max()
+    e = _check(lb, oracle, v, x, dtype)
+    assert e.max() <= (TOL64 if dtype == torch.float64 else TOL32), e.max()
+
+
+def test_temme_term_counts_binary32(lb):
+    """Binary32 Temme elements stop at the binary32 truncation (fewer terms
+    than binary64 on the same points) and run no integral."""
+    g = np.random.default_rng(42)
+    v = torch.from_numpy(g.uniform(0.0, 8.9, 4000)).cuda()
+    x = torch.from_numpy(10 ** g.uniform(-6, np.log10(1.25), 4000)).cuda()
+    v = v[(v - v.round()).abs() > 1e-3]
+    x = x[:v.numel()]
+    k64 = lb.k_terms(v, x)
+    k32 = lb.k_terms(v.float(), x.float())
+    assert int(k64.min()) >= 1 and int(k32.min()) >= 1
+    assert (k32 <= k64).all() and float(k32.double().mean()) < float(k64.double().mean())
+    assert int(lb.k_nodes(v.float(), x.float()).max()) == 0
