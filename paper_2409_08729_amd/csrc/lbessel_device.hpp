@@ -1069,9 +1069,10 @@ template <> struct TabInt<float> {
 __device__ __forceinline__ double k_up_ratio(double d, double mu, int n, double x) {
     const double ix2 = 2.0 * lrcp(x);
     const double a0 = mu * ix2;
-    double kn = 1.0;
+    double kn = 1.0, jd = 0.0;
     for (int j = 1; j < n; ++j) {
-        const double knew = fma(fma(double(j), ix2, a0), kn, d);
+        jd += 1.0;
+        const double knew = fma(fma(jd, ix2, a0), kn, d);
         d = kn;
         kn = knew;
     }
@@ -1185,14 +1186,14 @@ __device__ __forceinline__ T br_k_temme(T v, T x, int *nterms = nullptr) {
     }
     if (nterms != nullptr)
         *nterms = k;
-    if (n == T(0))
-        return llog(s0);
-    const T k1 = s1 * (T(2) * lrcp(x));                       // K_{mu+1}
-    const T l1 = llog(k1);
-    if (n == T(1))
-        return l1;
-    return l1 + T(llog(k_up_ratio(double(s0) * lrcp(double(k1)), double(mu), int(n),
-                                  double(x))));
+    // one logarithm for every order step count (lanes of one wave differ):
+    // K_v = K_mu (n = 0), K_{mu+1} (n = 1) or K_{mu+1} times the ratio of the
+    // recurrence, at most ~1e165 for x >= 1e-10, in binary64
+    const double k1 = double(s1) * (2.0 * lrcp(double(x)));     // K_{mu+1}
+    const double kv = (n == T(0)) ? double(s0)
+                                  : k1 * k_up_ratio(double(s0) * lrcp(k1), double(mu), int(n),
+                                                    double(x));
+    return T(llog(kv));
 }
 
 template <typename T, int KIND>
