@@ -124,15 +124,16 @@ int lbessel_log_kv_integral_f64(const double *v, const double *x, double *out,
  * expansion of log K_v(x) + x + log(2x/pi)/2 in 1/x on 2 < x <= 17.5; the
  * Hankel expansion above the thresholds of the general path), the orders of
  * the paper's v = 0, 1 comparisons (Sec. "Precision", Tables 5 and 7).
- * Integer orders 2..14 (|v| for K) take an integer-order path: where the
- * general path would sum the I series, a polynomial with the exact constant
- * coefficients n!/(k!(k+n)!) (DLMF 10.25.2); where it would integrate K,
- * the forward recurrence K_{j+1} = K_{j-1} + (2j/x) K_j (DLMF 10.29.1) from
- * K_0 and K_1 of the order-0/1 path (every term positive: stable); elsewhere
- * the general path's Hankel / Debye code, with the same bits.
- * Every other order runs the general path with v broadcast, bit-identical to
- * lbessel_log_{iv,kv}_{f64,f32} on an array filled with v.  Special values
- * follow the general conventions.
+ * Integer orders 2..14 of I take an integer-order path: where the general
+ * path would sum the I series, a polynomial with the exact constant
+ * coefficients n!/(k!(k+n)!) (DLMF 10.25.2); elsewhere the general path's
+ * Hankel / Debye code, with the same bits.  Every other order, and every
+ * other order of K, runs the general path with v broadcast, bit-identical to
+ * lbessel_log_{iv,kv}_{f64,f32} on an array filled with v (for the integer
+ * orders 2..14 of K its fallback runs the forward recurrence
+ * K_{j+1} = K_{j-1} + (2j/x) K_j, DLMF 10.29.1, from K_0 and K_1 of the
+ * order-0/1 path: every term positive, stable).  Special values follow the
+ * general conventions.
  */
 int lbessel_log_iv_order_f64(double v, const double *x, double *out, int64_t n,
                              void *stream);

@@ -1058,8 +1058,10 @@ int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out, in
 }  // extern "C"
 
 // Scalar order: orders 0 and 1 take the polynomial kernel, integer orders
-// 2..14 the integer-order kernel, every other order the grouped kernel with
-// the order broadcast.
+// 2..14 of I the integer-order kernel, every other order the grouped kernel
+// with the order broadcast (for K's integer orders its fallback runs the
+// same integer-order code, and the grouping keeps the recurrence and the
+// Hankel elements in separate chunks: 0.31 -> 0.20 ms for 20M x in [0, 150)).
 template <typename T, int KIND>
 static int run_order(T v, const T *x, T *out, int64_t n, hipStream_t st) {
     if (n < 0)
@@ -1081,12 +1083,14 @@ static int run_order(T v, const T *x, T *out, int64_t n, hipStream_t st) {
                                out, n);
         return launch_status();
     }
-    if (av == rint(av) && av >= T(tables::kIntOrderMin) && av <= T(tables::kIntOrderMax)) {
-        if (!grid_ok(n, kThreads, &blocks))
-            return LBESSEL_EINVAL;
-        hipLaunchKernelGGL((k_order_int<T, KIND>), dim3(blocks), dim3(kThreads), 0, st, int(av),
-                           x, out, n);
-        return launch_status();
+    if constexpr (KIND == KIND_I) {
+        if (av == rint(av) && av >= T(tables::kIntOrderMin) && av <= T(tables::kIntOrderMax)) {
+            if (!grid_ok(n, kThreads, &blocks))
+                return LBESSEL_EINVAL;
+            hipLaunchKernelGGL((k_order_int<T, KIND>), dim3(blocks), dim3(kThreads), 0, st,
+                               int(av), x, out, n);
+            return launch_status();
+        }
     }
     Args<T> a{nullptr, x, nullptr, out, n, v, T(0)};
     return launch_grouped<T, KIND, OP_LOG>(a, st);

@@ -1,10 +1,11 @@
 """Scalar-order entry points: orders 0 and 1 take the polynomial fast path
 (checked against the binary128 oracle, f64 and f32, over the whole argument
-range and across every internal boundary); integer orders 2..14 take the
-integer-order path (constant-coefficient I series, forward K recurrence from
-K_0 and K_1; oracle-checked, and equal to the general path's bits outside its
-series/integral region); any other order runs the general path with v
-broadcast and must give the array path's bits.  The array path of log K runs
+range and across every internal boundary); integer orders 2..14 of I take the
+integer-order path (constant-coefficient series; oracle-checked, and equal to
+the general path's bits outside its series region), those of K the general
+path, whose fallback runs the forward recurrence from K_0 and K_1 (oracle-
+checked, the array path's bits everywhere); any other order runs the general
+path with v broadcast and must give the array path's bits.  The array path of log K runs
 the same integer-order code for integer orders 0..14 at x >= 1e-10, also
 inside tiles that mix them with other orders."""
 import numpy as np
@@ -145,8 +146,9 @@ def test_integer_orders_match_oracle(lb, oracle, kind, dtype):
 @pytest.mark.parametrize("kind", ["I", "K"])
 def test_integer_orders_outside_their_region_equal_general_path(lb, kind, dtype):
     """Where the general path runs the Hankel or Debye branch for order n,
-    the integer-order path runs the same code: same bits; also the special
-    values and negative orders for K."""
+    the integer-order path of I runs the same code: same bits; K's scalar
+    integer orders run the general path itself, so every element matches;
+    also the special values and negative orders for K."""
     x = torch.from_numpy(_xgrid(7)).to("cuda:0", dtype)
     f_ord = lb.log_iv_order if kind == "I" else lb.log_kv_order
     f_arr = lb.log_iv if kind == "I" else lb.log_kv
@@ -154,7 +156,7 @@ def test_integer_orders_outside_their_region_equal_general_path(lb, kind, dtype)
     for n in INT_ORDERS:
         vv = torch.full_like(x, float(n))
         br = lb.classify(kind, vv, x)
-        keep = br != 2                     # Hankel, Debye or special value
+        keep = (br != 2) if kind == "I" else torch.ones_like(br, dtype=torch.bool)
         a = f_ord(float(n), x)
         b = f_arr(vv, x)
         assert torch.equal(a[keep].view(it), b[keep].view(it)), (kind, n)
