@@ -1070,12 +1070,17 @@ __device__ __forceinline__ double k_up_ratio(double d, double mu, int n, double 
     const double ix2 = 2.0 * lrcp(x);
     const double a0 = mu * ix2;
     double kn = 1.0, jd = 0.0;
-    for (int j = 1; j < n; ++j) {
-        jd += 1.0;
-        const double knew = fma(fma(jd, ix2, a0), kn, d);
-        d = kn;
-        kn = knew;
+    int j = 1;
+    // two steps per trip (no register shuffle between them), then the odd one
+    for (; j + 1 < n; j += 2) {
+        const double k1 = fma(fma(jd + 1.0, ix2, a0), kn, d);
+        const double k2 = fma(fma(jd + 2.0, ix2, a0), k1, kn);
+        jd += 2.0;
+        d = k1;
+        kn = k2;
     }
+    if (j < n)
+        kn = fma(fma(jd + 1.0, ix2, a0), kn, d);
     return kn;
 }
 
@@ -1181,7 +1186,8 @@ __device__ __forceinline__ T br_k_temme(T v, T x, int *nterms = nullptr) {
         s0 = fma(c, f, s0);
         s1 = fma(c, fma(-kk, f, p), s1);
         const T eps = Cst<T>::series_eps;
-        if (c * fabs(f) <= eps * s0 && c * fma(kk, fabs(f), fabs(p)) <= eps * s1)
+        // both parts tested without a short circuit: one branch per term
+        if ((c * fabs(f) <= eps * s0) & (c * fma(kk, fabs(f), fabs(p)) <= eps * s1))
             break;
     }
     if (nterms != nullptr)
