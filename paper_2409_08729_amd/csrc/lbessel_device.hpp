@@ -456,10 +456,13 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     // and enters through log1p: where I_v(x) is close to (x/2)^v / Gamma(v+1)
     // (small x) its log stays accurate relative to the small correction.
     const T q2 = q * q;
+    const T q_2 = T(2) * q;
     T term = T(1);
     T sum = T(0);
+    T f0 = T(-1);
     for (int k = 1; k < 200; k += 2) {
-        const T f0 = T(k), f1 = T(k + 1);
+        f0 += T(2);
+        const T f1 = f0 + T(1);
         const T d0 = f0 * (f0 + v);
         const T d1 = f1 * (f1 + v);
         const T r = lrcp(d0 * d1);
@@ -467,7 +470,8 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
         term = term * q2 * r;
         sum = sum + t0;
         sum = sum + term;
-        if (d1 > T(2) * q && term < fma(Cst<T>::series_eps, sum, Cst<T>::series_eps))
+        // both conditions without a short circuit: one branch per pair
+        if ((d1 > q_2) & (term < fma(Cst<T>::series_eps, sum, Cst<T>::series_eps)))
             break;
     }
     T lg;
@@ -1123,8 +1127,9 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
 //   f_k = (k f_{k-1} + p_{k-1} + q_{k-1}) / (k^2 - mu^2),
 //   p_k = p_{k-1} / (k - mu),  q_k = q_{k-1} / (k + mu),
 // (G1, G2, sin(pi mu)/(pi mu) as polynomials in mu^2, generated tables), the
-// sum stopped once a term's parts fall below 2^-56 of both sums (the c_k
-// fall faster than geometrically for x <= 1.25); then the upward recurrence
+// sum stopped once c_k (k |f_k| + |p_k|), which bounds both new terms, falls
+// below 2^-56 of the smaller sum (the c_k fall faster than geometrically for
+// x <= 1.25); then the upward recurrence
 // K_{nu+1} = K_{nu-1} + (2 nu / x) K_nu (DLMF 10.29.1) from nu = mu + 1 to v
 // (k_up_ratio), as in the integer-order path.  One reciprocal per term:
 // 1/(k - mu) = (k + mu)/(k^2 - mu^2) and likewise; 1/k from a table (k is the
@@ -1185,9 +1190,9 @@ __device__ __forceinline__ T br_k_temme(T v, T x, int *nterms = nullptr) {
         q = q * (kk - mu) * d;
         s0 = fma(c, f, s0);
         s1 = fma(c, fma(-kk, f, p), s1);
-        const T eps = Cst<T>::series_eps;
-        // both parts tested without a short circuit: one branch per term
-        if ((c * fabs(f) <= eps * s0) & (c * fma(kk, fabs(f), fabs(p)) <= eps * s1))
+        // c (k |f| + |p|) bounds both new terms (k >= 1): one test against the
+        // smaller sum
+        if (c * fma(kk, fabs(f), fabs(p)) <= Cst<T>::series_eps * fmin(s0, s1))
             break;
     }
     if (nterms != nullptr)
