@@ -921,13 +921,13 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     // lands in the last bucket)
     const float vf = float(v), xf = fmaxf(float(x), 1e-30f);
     if (TEMME && x <= tables::kTemmeX) {
-        // Temme's series: ~2.5 units per term (the term count grows with x)
-        // and one per order step above mu + 1; x < 1e-10 (small-argument
-        // forms, ~2 terms' worth) lands in the cheapest series bucket
+        // Temme's series: ~4.7 order steps' worth per term (the term count
+        // grows with x; measured 26.8 and 5.7 instructions) and one unit per
+        // order step above mu + 1
         const float nt = (xf < 1e-4f) ? 2.0f : (xf < 1e-2f) ? 3.5f : (xf < 0.1f) ? 5.5f
                          : (xf < 0.4f) ? 7.5f : 10.0f;
-        const float est = fmaf(2.5f, nt, fmaxf(rintf(vf) - 1.0f, 0.0f));
-        return (est < 10.0f) ? 0 : (est < 16.0f) ? 1 : (est < 22.0f) ? 2 : 3;
+        const float est = fmaf(4.7f, nt, fmaxf(rintf(vf) - 1.0f, 0.0f));
+        return (est < 20.0f) ? 0 : (est < 30.0f) ? 1 : (est < 42.0f) ? 2 : 3;
     }
     float w;
     if (v * v > x) {
