@@ -1,9 +1,12 @@
 """The log K fallback on the GPU against values fixed outside the oracle.
 
-The fallback integrates K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt by the
-trapezoid rule (x >= 1e-10) and uses the small-argument form below; the
-oracle integrates the same integral, so these tests pin the GPU result on
-the fallback's whole region without it:
+The fallback (x >= 1e-10) runs the order recurrence from K_0, K_1 at integer
+orders, Temme's series at the fractional order plus the same recurrence up to
+x = 1.25, and above it the trapezoid rule on K_v(x) = int_0^inf
+exp(-x cosh t) cosh(v t) dt; below x = 1e-10 the small-argument form.  The
+oracle integrates that same integral, so these tests pin the GPU result on
+the fallback's whole region without it (half-integer orders are Temme's
+series at mu = +-1/2 up to x = 1.25, integer orders the integer-order path):
   * half-integer orders n + 1/2, n = 0..14: the finite sum of DLMF 10.49.12;
   * integer orders n = 0..14: the expansion of DLMF 10.31.1;
 both evaluated in decimal arithmetic (tests/closed_forms.py) on a dense
