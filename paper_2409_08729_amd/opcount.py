@@ -24,10 +24,11 @@ Reduce (host):
 
 merges the probed sets into paper_2409_08729_amd/opmodel.json.  The I series
 branch is probed at one point (its trip count varies mildly with (v, x)).
-The K fallback's cost is setup + per_node x nodes, fitted by least squares
-over eight points with different node counts (the fit residuals are
-recorded); a launch's algorithmic ops then use each element's own node
-count.
+The K fallback's integral costs setup + per_node x nodes, fitted by least
+squares over eight (binary32) or ten (binary64) points with different node
+counts; Temme's series setup + per_term x terms + per_step x order steps,
+fitted the same way over its probe points; the fit residuals are recorded.
+A launch's algorithmic ops then use each element's own node and term count.
 """
 from __future__ import annotations
 
