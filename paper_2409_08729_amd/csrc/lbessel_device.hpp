@@ -909,8 +909,8 @@ __device__ __forceinline__ int i_cost_bucket(T x) {
 // after the other in chunks shared with the single walk of windows that
 // start at 0.  With TEMME (the default variant) buckets 0..3 hold the
 // Temme-series elements (x <= 1.25) by term and order-step estimate, and
-// the integer orders; 4, 5 and 6 the integral's.  Only used to order work
-// inside a tile; any value is correct.
+// the integer orders; bucket 4 every integral element (5 and 6 stay
+// empty).  Only used to order work inside a tile; any value is correct.
 template <int B, bool TEMME>
 __device__ __forceinline__ int k_cost_bucket(double v, double x) {
     static_assert(B == 7, "six cost buckets and the interior-window class");
@@ -929,6 +929,12 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
         const float est = fmaf(4.7f, nt, fmaxf(rintf(vf) - 1.0f, 0.0f));
         return (est < 20.0f) ? 0 : (est < 30.0f) ? 1 : (est < 42.0f) ? 2 : 3;
     }
+    // the integral's elements above the series bound (and x < 1e-10): one
+    // bucket, the costliest in list order; the node-count estimate below
+    // cost more than its ordering saved there (K stress grid f64 1.43-1.44
+    // -> 1.39 ms, f32 0.91-0.92 -> 0.82 ms)
+    if (TEMME)
+        return 4;
     float w;
     if (v * v > x) {
         const float q = vf * fm::rcp_hw(xf);
@@ -951,8 +957,6 @@ __device__ __forceinline__ int k_cost_bucket(double v, double x) {
         w = fm::log_hw(1.0f + a + fm::sqrt_hw(a * (2.0f + a)));   // acosh(1 + 45/x)
     }
     const float est = w * fmaf(0.05f, vf, 1.0f) * (1.0f / 0.25f);
-    if (TEMME)   // integral elements above the series bound: x > 1.25 or x < 1e-10
-        return (x < 1e-10) ? 3 : (est < 33.0f) ? 4 : 5;
     return (est < 19.0) ? 0 : (est < 29.0) ? 1 : (est < 37.0) ? 2 : (est < 45.0) ? 3
                                                                  : (est < 55.0) ? 4 : 5;
 }

@@ -184,7 +184,8 @@ template <int NV, int NTH = kThreads> struct TileCfg {
 // the K integral's node count and the I series' term count.  For the
 // one-order operations the fallback is therefore split into buckets by an
 // estimate of that count (kKBuckets for K: six by node count and one for the
-// interior windows; kIBuckets for I), so the lanes of one 64-entry chunk run
+// interior windows; in the default variant four by Temme-series cost and one
+// for the integral; kIBuckets for I), so the lanes of one 64-entry chunk run
 // loops of similar length.  List order: costliest
 // bucket first, then the cheaper ones, Debye, Hankel.
 // The Debye class is split the same way into its term-count tiers (U_13,
