@@ -1050,7 +1050,7 @@ __device__ __forceinline__ T order01(T x) {
 //      polynomial with the exact constant coefficients n!/(k!(k+n)!)
 //      (DLMF 10.25.2): no divisions and one trip count for every argument;
 //   K: the forward recurrence K_{j+1} = K_{j-1} + (2j/x) K_j (DLMF 10.29.1)
-//      from K_0 and K_1 of the order-0/1 path (k_up_ratio: values scaled to
+//      from K_0 and K_1 of the order-0/1 path (k_up: values scaled to
 //      K_1 = 1, in binary64).  Both terms are positive, so nothing cancels:
 //      about one rounding per step.  log K_n = log K_1 + log(K_n / K_1).
 //      Below x = 1e-10 the small-argument form of the general path.
@@ -1066,18 +1066,17 @@ template <> struct TabInt<float> {
     static __device__ __forceinline__ const float *logfact() { return tables::kLogFact32; }
 };
 
-// K_{mu+n} / K_{mu+1} by the recurrence K_{nu+1} = K_{nu-1} + (2 nu / x) K_nu
-// (DLMF 10.29.1), nu = mu + 1 .. mu + n - 1, on values scaled so that
-// K_{mu+1} = 1 (d = K_mu / K_{mu+1} on entry): one fma per step, no
+// K_{mu+n} (n >= 1) by the recurrence K_{nu+1} = K_{nu-1} + (2 nu / x) K_nu
+// (DLMF 10.29.1), nu = mu + 1 .. mu + n - 1, from d = K_mu and k1 = K_{mu+1}
+// (or both scaled by one factor), ix2 = 2/x: one fma per step, no
 // reciprocal.  For mu >= -1/2 every term is positive (K grows with the
 // order), so nothing cancels and each step adds about one rounding.  In
-// binary64 for both precisions: the ratio stays in [1, ~1e160] for n <= 15
-// and x >= 1e-10 (each step at most 1 + 2 (mu + 14) / x), so it needs no
-// rescaling there.
-__device__ __forceinline__ double k_up_ratio(double d, double mu, int n, double x) {
-    const double ix2 = 2.0 * lrcp(x);
+// binary64 for both precisions: K_{mu+n} / K_{mu+1} stays in [1, ~1e160] for
+// n <= 15 and x >= 1e-10 (each step at most 1 + 2 (mu + 14) / x), so values
+// with K_{mu+1} below 1e140 need no rescaling there.
+__device__ __forceinline__ double k_up(double d, double k1, double mu, int n, double ix2) {
     const double a0 = mu * ix2;
-    double kn = 1.0, jd = 0.0;
+    double kn = k1, jd = 0.0;
     int j = 1;
     // two steps per trip (no register shuffle between them), then the odd one
     for (; j + 1 < n; j += 2) {
@@ -1113,7 +1112,7 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
         return T(br_k_small_x(double(v), double(x)));
     const T l0 = order01<T, KIND_K, 0>(x);
     const T l1 = order01<T, KIND_K, 1>(x);
-    return l1 + T(llog(k_up_ratio(double(lexp(l0 - l1)), 0.0, n, double(x))));
+    return l1 + T(llog(k_up(double(lexp(l0 - l1)), 1.0, 0.0, n, 2.0 * lrcp(double(x)))));
 }
 
 // ---------------------------------------------------------------------------
@@ -1135,7 +1134,7 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
 // below 2^-56 of the smaller sum (the c_k fall faster than geometrically for
 // x <= 1.25); then the upward recurrence
 // K_{nu+1} = K_{nu-1} + (2 nu / x) K_nu (DLMF 10.29.1) from nu = mu + 1 to v
-// (k_up_ratio), as in the integer-order path.  One reciprocal per term:
+// (k_up), as in the integer-order path.  One reciprocal per term:
 // 1/(k - mu) = (k + mu)/(k^2 - mu^2) and likewise; 1/k from a table (k is the
 // same in every lane of a wave).
 // Cost ~150 + ~20 per term (2..11 terms) + ~8 per order step, against
@@ -1177,9 +1176,13 @@ __device__ __forceinline__ T br_k_temme(T v, T x, int *nterms = nullptr) {
     else
         shs = (e - ie) * (T(0.5) * lrcp(s));
     const T ch = T(0.5) * (e + ie);
-    T f = fma(g1, ch, shs * L * g2) * lrcp(sinc);
-    T p = T(0.5) * e * lrcp(fma(-mu, g1, g2));                // 1/Gamma(1+mu) = G2 - mu G1
-    T q = T(0.5) * ie * lrcp(fma(mu, g1, g2));                // 1/Gamma(1-mu) = G2 + mu G1
+    const T rs = lrcp(sinc);                                  // Gamma(1+mu) Gamma(1-mu)
+    T f = fma(g1, ch, shs * L * g2) * rs;
+    // 1/Gamma(1-mu) = G2 + mu G1 and 1/Gamma(1+mu) = G2 - mu G1, so by the
+    // reflection formula Gamma(1+mu) = rs (G2 + mu G1), Gamma(1-mu) = rs (G2 - mu G1)
+    const T hr = T(0.5) * rs;
+    T p = hr * e * fma(mu, g1, g2);
+    T q = hr * ie * fma(-mu, g1, g2);
     const T qx = T(0.25) * x * x;
     const LB_CONST_AS T *ik = opaque_const<T>(TabTm<T>::invk());
     T c = T(1), s0 = f, s1 = p, kk = T(0);
@@ -1202,12 +1205,11 @@ __device__ __forceinline__ T br_k_temme(T v, T x, int *nterms = nullptr) {
     if (nterms != nullptr)
         *nterms = k;
     // one logarithm for every order step count (lanes of one wave differ):
-    // K_v = K_mu (n = 0), K_{mu+1} (n = 1) or K_{mu+1} times the ratio of the
-    // recurrence, at most ~1e165 for x >= 1e-10, in binary64
-    const double k1 = double(s1) * (2.0 * lrcp(double(x)));     // K_{mu+1}
+    // K_v = K_mu (n = 0), else the recurrence from K_mu, K_{mu+1} in binary64
+    // (K_{mu+1} < 2e15 and K_v < 1e181 for x >= 1e-10, v < 15)
+    const double ix2 = 2.0 * lrcp(double(x));
     const double kv = (n == T(0)) ? double(s0)
-                                  : k1 * k_up_ratio(double(s0) * lrcp(k1), double(mu), int(n),
-                                                    double(x));
+                                  : k_up(double(s0), double(s1) * ix2, double(mu), int(n), ix2);
     return T(llog(kv));
 }
 
