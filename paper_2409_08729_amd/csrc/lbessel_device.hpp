@@ -1137,8 +1137,9 @@ __device__ __forceinline__ T order_int_fb(int n, T x) {
 // (k_up), as in the integer-order path.  One reciprocal per term:
 // 1/(k - mu) = (k + mu)/(k^2 - mu^2) and likewise; 1/k from a table (k is the
 // same in every lane of a wave).
-// Cost ~150 + ~20 per term (2..11 terms) + ~8 per order step, against
-// ~290 + ~38 per node (20..70 nodes there) for the integral; the series is
+// Cost (VALU instructions, binary64) ~205 + ~27 per term (2..11 terms) + ~5
+// per order step, against ~145 + ~41 per node (20..70 nodes there) for the
+// integral; the series is
 // independent of the integral representations (the paper's and DLMF 10.32.9).
 // Binary32: the same with binary32 tables and stop rule (2^-27), the order
 // recurrence in binary64.  nterms, if given, receives the number of series
