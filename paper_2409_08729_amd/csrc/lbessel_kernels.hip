@@ -215,13 +215,16 @@ template <int KIND, int OP, int VAR> struct Classes {
 // little more there and lose on launches of one class, whose 16-wave
 // workgroups wait at the tile barrier with little else to overlap).  Their
 // LDS grows with the tile (16 bytes of staging per element): four
-// workgroups per CU, 32 waves.  The other kernels keep 256 threads.
+// workgroups per CU, 32 waves.  Binary64 only: the binary32 K kernels are
+// ~2% faster on 1024-element tiles (stress grid 0.81-0.83 -> 0.80 ms, the
+// per-order sets ~1%), as are the other kernels, which keep 256 threads.
 #ifndef LBESSEL_K_THREADS
 #define LBESSEL_K_THREADS 512
 #endif
-template <int KIND, int OP, int VAR> struct GroupShape {
+template <typename T, int KIND, int OP, int VAR> struct GroupShape {
     static constexpr int threads =
-        (KIND == KIND_K && OpTraits<OP>::nv == 1 && (VAR == VAR_DEFAULT || VAR == VAR_PAPER_REGIMES))
+        (KIND == KIND_K && sizeof(T) == 8 && OpTraits<OP>::nv == 1 &&
+         (VAR == VAR_DEFAULT || VAR == VAR_PAPER_REGIMES))
             ? LBESSEL_K_THREADS
             : kThreads;
     // LDS-bound at 4 (or 2) workgroups per CU: 8 waves per SIMD (<= 64 VGPRs)
@@ -522,16 +525,16 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
 }
 
 template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
-__global__ __launch_bounds__((GroupShape<KIND, OP, VAR>::threads))
-__attribute__((amdgpu_waves_per_eu(GroupShape<KIND, OP, VAR>::waves_per_eu)))
+__global__ __launch_bounds__((GroupShape<T, KIND, OP, VAR>::threads))
+__attribute__((amdgpu_waves_per_eu(GroupShape<T, KIND, OP, VAR>::waves_per_eu)))
 void k_grouped(Args<T> a) {
-    grouped_tile<T, KIND, OP, VAR, GroupShape<KIND, OP, VAR>::threads>(a, blockIdx.x);
+    grouped_tile<T, KIND, OP, VAR, GroupShape<T, KIND, OP, VAR>::threads>(a, blockIdx.x);
 }
 
 // Launch of k_grouped over a.n elements with its workgroup size and tile.
 template <typename T, int KIND, int OP, int VAR = VAR_DEFAULT>
 int launch_grouped(const Args<T> &a, hipStream_t st) {
-    constexpr int nth = GroupShape<KIND, OP, VAR>::threads;
+    constexpr int nth = GroupShape<T, KIND, OP, VAR>::threads;
     constexpr int tile = TileCfg<OpTraits<OP>::nv, nth>::tile;
     const int64_t b = (a.n + tile - 1) / tile;
     if (b > int64_t(0x7fffffff))
