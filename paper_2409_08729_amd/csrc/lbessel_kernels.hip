@@ -236,15 +236,16 @@ template <typename T, int KIND, int OP, int VAR> struct GroupShape {
 // slots in step 4, so HBM sees one coalesced read of (v, x) and one coalesced
 // write of the results per element, however long the tile's integrals take,
 // and step 4 reads its operands from LDS instead of waiting on L2.  The
-// binary64 I kernels do without: their 16 KB of staging would cut them from
-// 8 workgroups per CU to 6, which costs more than the L2 re-reads.  The
-// two-order operations finish a tile quickly enough that the step-4 re-reads
-// hit L2.
-template <typename T, int NV, int NC, bool STAGE, int NTH> struct Smem {
+// binary64 I kernels stage the arguments alone (XS): 16 KB of full staging
+// would cut them from 8 workgroups per CU to 6, which costs more than the
+// re-reads of the orders (stress grid 0.98-1.00 -> 0.95 ms with the
+// arguments staged; 2-5% slower fully staged).  The two-order operations
+// finish a tile quickly enough that the step-4 re-reads hit L2.
+template <typename T, int NV, int NC, bool STAGE, int NTH, bool XS = false> struct Smem {
     using Cfg = TileCfg<NV, NTH>;
     static constexpr int NW = NTH / 64;
     T sv[STAGE ? Cfg::tile : 1];                         // order, then result
-    T sx[STAGE ? Cfg::tile : 1];                         // argument
+    T sx[(STAGE || XS) ? Cfg::tile : 1];                 // argument
     uint16_t list[Cfg::tile * NV];                       // evaluation ids, class-sorted
     uint16_t cnt[NC][Cfg::slots][NW];                    // counts, then offsets
     int start[NC];                                       // first list position per class
@@ -277,7 +278,10 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
     static_assert(NC < 32, "class masks fit 32 bits");
     static_assert(TILE * NV <= 65536, "evaluation ids fit 16 bits");
     constexpr bool STAGE = (NV == 1) && (KIND == KIND_K || sizeof(T) == 4);
-    __shared__ Smem<T, NV, NC, STAGE, NTH> sm;
+    // binary64 log I stages the arguments alone (8 KB: still 8 workgroups
+    // per CU), so step 4 re-reads only the orders from L2 or HBM
+    constexpr bool XSTAGE = (NV == 1) && !STAGE && (VAR == VAR_DEFAULT);
+    __shared__ Smem<T, NV, NC, STAGE, NTH, XSTAGE> sm;
 
     // the fallback's tables, loaded below only if the tile has fallback work
     FbTab<KIND, T> *kt = fb_tab_storage<KIND, T>();
@@ -318,6 +322,8 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             } else if (NV == 1) {
                 if (STAGE) {
                     sm.sv[e] = v;
+                    sm.sx[e] = x;
+                } else if (XSTAGE) {
                     sm.sx[e] = x;
                 }
                 const int br = classify_var<T, KIND, VAR>(v, x);
@@ -482,7 +488,7 @@ __device__ __forceinline__ void grouped_tile(const Args<T> &a, int64_t tile) {
             } else {
                 const int64_t i = base + e;
                 const T v = order_of<T, KIND, OP>(a, i);
-                const T x = a.x[i];
+                const T x = XSTAGE ? sm.sx[e] : a.x[i];
                 const T y = eval_branch<T, KIND, VAR>(b, v + T(sub), x, kt);
                 if (NV == 2)
                     sm.res[id] = y;
