@@ -122,8 +122,10 @@ int lbessel_log_kv_integral_f64(const double *v, const double *x, double *out,
  * polynomials with constant coefficients (power series of I_0, I_1, DLMF
  * 10.25.2; small-argument series of K_0, K_1, DLMF 10.31.1; a Chebyshev
  * expansion of log K_v(x) + x + log(2x/pi)/2 in 1/x on 2 < x <= 17.5; the
- * Hankel expansion above the thresholds of the general path), the orders of
- * the paper's v = 0, 1 comparisons (Sec. "Precision", Tables 5 and 7).
+ * Hankel expansion above the thresholds of the general path; in binary32,
+ * order 1 between the Debye and Hankel bounds of x, the Debye branch as in
+ * the general path), the orders of the paper's v = 0, 1 comparisons (Sec.
+ * "Precision", Tables 5 and 7).
  * Integer orders 2..14 of I take an integer-order path: where the general
  * path would sum the I series, a polynomial with the exact constant
  * coefficients n!/(k!(k+n)!) (DLMF 10.25.2); elsewhere the general path's

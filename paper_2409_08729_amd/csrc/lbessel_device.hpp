@@ -79,6 +79,11 @@ __device__ __forceinline__ double lexp_b(double a) { return fm::exp64_bounded(a)
 // and series denominators >= 1)
 __device__ __forceinline__ double lrcp(double a) { return fm::rcp64(a); }
 __device__ __forceinline__ float lrcp(float a) { return fm::rcp_hw(a); }
+__device__ __forceinline__ double lrsq(double a) { return fm::rsq64(a); }
+__device__ __forceinline__ float lrsq(float a) {   // v_rsq_f32 and one Newton step
+    const float y = fm::rsqrt_hw(a);
+    return fmaf(0.5f * y, fmaf(-a * y, y, 1.0f), y);
+}
 __device__ __forceinline__ float lexp_b(float a) { return expf(a); }
 
 // ---------------------------------------------------------------------------
@@ -341,24 +346,25 @@ __device__ __forceinline__ T br_u_wide(T v, T x, int nt) {
         return T(0.5) * (Cst<T>::log_pi_2 - lvr) - v * eta + ls;
 }
 
-// Below safe_big every reciprocal and product below is a normal number:
-// x/v and z/(1 + r) by a reciprocal and one correction step (~0.5 ulp, they
-// enter v eta), 1/r and 1/v by reciprocals, and log|1 + acc| - log(v r)/2 as
-// one logarithm, log((1 + acc)^2 / (v r)) / 2.
+// Below big_z (v^2 + x^2 stays finite) everything derives from one inverse
+// square root: with q = sqrt(v^2 + x^2) = v r, 1/(v r) = 1/q is the
+// expansion's step (w = t/v) and t = v/q, v eta = q + v log(x/(v + q))
+// (z/(1 + r) = x/(v + q)), the quotient by a reciprocal and one correction
+// step (~0.5 ulp: it enters v eta), and log|1 + acc| - log(v r)/2 as one
+// logarithm, log((1 + acc)^2 / q) / 2.
 template <typename T, int KIND, int NT = tables::kUTerms>
 // nt (<= NT, runtime): terms actually summed.  Terms above nt are skipped
 // per lane, so lanes of one wave with different nt cost the largest nt once,
 // and a term count gives the same bits whichever way it is reached.
 __device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
-    if (!(v < Cst<T>::safe_big && x < Cst<T>::safe_big))
+    if (!(v < Cst<T>::big_z && x < Cst<T>::big_z))
         return br_u_wide<T, KIND, NT>(v, x, nt);
-    const T iv = lrcp(v);
-    T z = x * iv;
-    z = fma(fma(-z, v, x), iv, z);
-    const T r = (z < Cst<T>::big_z) ? sqrt(fma(z, z, T(1))) : z;
-    const T t = lrcp(r);
+    const T s2 = fma(v, v, x * x);
+    const T iq = lrsq(s2);                                   // 1/(v r)
+    const T q = s2 * iq;                                     // v r
+    const T t = v * iq;
     const T p = t * t;
-    const T w = (KIND == KIND_I ? t : -t) * iv;
+    const T w = (KIND == KIND_I ? iq : -iq);
     const LB_CONST_AS T *P = opaque_const<T>(&debye_table<T>()[0][0]);
     T acc = T(0);
 #pragma unroll
@@ -372,21 +378,21 @@ __device__ __forceinline__ T br_u(T v, T x, int nt = NT) {
             pk = fm::fma_c(pk, p, row[j]);
         acc = w * (pk + acc);
     }
-    const T d = T(1) + r;
+    const T d = v + q;
     const T id = lrcp(d);
-    T zq = z * id;
-    zq = fma(fma(-zq, d, z), id, zq);
-    // z below the normal range (x/v < ~1e-290 in f64): log z from log x - log v
+    T zq = x * id;
+    zq = fma(fma(-zq, d, x), id, zq);
+    // x/(v + q) below the normal range (x/v < ~1e-290 in f64): log x - log(v + q)
     T lz = llog(zq);
-    if (z < Cst<T>::tiny_z)
-        lz = llog(x) - llog(v) - llog(d);
-    const T eta = r + lz;
+    if (x < Cst<T>::tiny_z * v)
+        lz = llog(x) - llog(d);
+    const T veta = fma(v, lz, q);                            // v eta
     const T s1 = fabs(T(1) + acc);
-    const T lq = llog(s1 * s1 * (t * iv));
+    const T lq = llog(s1 * s1 * iq);
     if (KIND == KIND_I)
-        return v * eta - T(0.5) * Cst<T>::log_2pi + T(0.5) * lq;
+        return veta - T(0.5) * Cst<T>::log_2pi + T(0.5) * lq;
     else
-        return T(0.5) * (Cst<T>::log_pi_2 + lq) - v * eta;
+        return T(0.5) * (Cst<T>::log_pi_2 + lq) - veta;
 }
 
 // ---------------------------------------------------------------------------

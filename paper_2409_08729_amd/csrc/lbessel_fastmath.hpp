@@ -68,6 +68,19 @@ __host__ __device__ __forceinline__ double rcp64(double d) {
 #endif
 }
 
+// 1/sqrt(a) to within about one ulp: the hardware estimate (v_rsq_f64) and
+// two Newton steps y <- y + y (1 - a y^2) / 2, for normal a > 0 whose square
+// root and its reciprocal are normal (the host build divides).
+__host__ __device__ __forceinline__ double rsq64(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(a);
+    y = fma(0.5 * y, fma(-a * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-a * y, y, 1.0), y);
+#else
+    return 1.0 / sqrt(a);
+#endif
+}
+
 // ln 2 = kLn2Hi + kLn2Lo, kLn2Hi with 32 significant bits (k * kLn2Hi exact
 // for |k| < 2^21).
 constexpr double kLog2e = 0x1.71547652b82fep+0;

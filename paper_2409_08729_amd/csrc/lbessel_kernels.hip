@@ -646,8 +646,20 @@ __global__ __launch_bounds__(kThreads) void k_order01(const T *__restrict__ x,
         return;
     const T xx = x[i];
     T y;
-    if (!special_value<T, KIND>(T(V), xx, &y))
-        y = order01<T, KIND, V>(xx);
+    if (!special_value<T, KIND>(T(V), xx, &y)) {
+        // binary32 order 1: between x3 and x1 the regime takes the Debye
+        // branch (x3 < x1 there), so the scalar-order path does too and gives
+        // the array path's bits
+        constexpr RegimeSet r = Regime<T, KIND>::r;
+        if constexpr (V == 1 && r.x3 < r.x1 && 1.0 > r.v3) {
+            if (xx > T(r.x3) && !(xx > T(r.x1)))
+                y = br_u<T, KIND>(T(V), xx);
+            else
+                y = order01<T, KIND, V>(xx);
+        } else {
+            y = order01<T, KIND, V>(xx);
+        }
+    }
     out[i] = y;
 }
 
@@ -1067,7 +1079,8 @@ int lbessel_vmf_log_norm_grad_f64(const double *kappa, double p, double *out, in
 
 }  // extern "C"
 
-// Scalar order: orders 0 and 1 take the polynomial kernel, integer orders
+// Scalar order: orders 0 and 1 take the polynomial kernel (binary32 order 1
+// between the Debye and Hankel bounds of x: the Debye branch), integer orders
 // 2..14 of I the integer-order kernel, every other order the grouped kernel
 // with the order broadcast (for K's integer orders its fallback runs the
 // same integer-order code, and the grouping keeps the recurrence and the
