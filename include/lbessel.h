@@ -346,8 +346,10 @@ int lbessel_k_terms(int precision, const void *v, const void *x, int32_t *terms,
  * their accuracy where the kernels run them: out[i] = f(a[i]) with op
  * 0 = 1/a (hardware estimate and two Newton steps), 1 = exp(a), 2 = exp(a)
  * for |a| < 1e9 (the form the branches use on bounded arguments),
- * 3 = log(a), 4 = log(1 + a), a >= 0.  Device arrays of n elements; n = 0 is
- * a no-op; LBESSEL_EINVAL for another op, null pointers or n < 0.
+ * 3 = log(a), 4 = log(1 + a), a >= 0, 5 = 1/sqrt(a) for normal a > 0
+ * (hardware estimate and two Newton steps; the Debye branch's inverse square
+ * root).  Device arrays of n elements; n = 0 is a no-op; LBESSEL_EINVAL for
+ * another op, null pointers or n < 0.
  */
 int lbessel_elementary_f64(int op, const double *a, double *out, int64_t n,
                            void *stream);

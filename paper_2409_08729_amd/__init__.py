@@ -397,7 +397,7 @@ def k_nodes(v: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     return out
 
 
-ELEMENTARY = {"rcp": 0, "exp": 1, "exp_bounded": 2, "log": 3, "log1p": 4}
+ELEMENTARY = {"rcp": 0, "exp": 1, "exp_bounded": 2, "log": 3, "log1p": 4, "rsqrt": 5}
 
 
 def elementary(op: str, a: torch.Tensor) -> torch.Tensor:

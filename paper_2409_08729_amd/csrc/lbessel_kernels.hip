@@ -728,7 +728,7 @@ __global__ __launch_bounds__(kThreads) void k_elementary(int op, const double *a
         return;
     const double x = a[i];
     out[i] = (op == 0) ? lrcp(x) : (op == 1) ? lexp(x) : (op == 2) ? lexp_b(x)
-             : (op == 3) ? llog(x) : llog1p(x);
+             : (op == 3) ? llog(x) : (op == 4) ? llog1p(x) : lrsq(x);
 }
 
 // Series terms of the K fallback's Temme branch per element (after f_0); 0
@@ -1156,7 +1156,7 @@ int lbessel_k_nodes(int precision, const void *v, const void *x, int32_t *nodes,
 }
 
 int lbessel_elementary_f64(int op, const double *a, double *out, int64_t n, void *s) {
-    if (n < 0 || op < 0 || op > 4)
+    if (n < 0 || op < 0 || op > 5)
         return LBESSEL_EINVAL;
     if (n == 0)
         return LBESSEL_OK;

@@ -83,7 +83,8 @@ def test_diagnostic_argument_checks(lib):
     assert lib.lbessel_k_terms(32, None, None, None, -1, None) == -1
     assert lib.lbessel_k_terms(64, None, None, None, 5, None) == -1
     assert lib.lbessel_k_terms(16, None, None, None, 0, None) == -1
-    assert lib.lbessel_elementary_f64(5, None, None, 0, None) == -1
+    assert lib.lbessel_elementary_f64(6, None, None, 0, None) == -1
+    assert lib.lbessel_elementary_f64(5, None, None, 0, None) == 0
     assert lib.lbessel_elementary_f64(0, None, None, 0, None) == 0
     assert lib.lbessel_elementary_f64(3, None, None, 4, None) == -1
 

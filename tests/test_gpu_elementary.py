@@ -1,6 +1,6 @@
 """The library's binary64 elementary functions as the kernels run them
-(lbessel_elementary_f64: the hardware reciprocal with two Newton steps, the
-exp and log sequences of csrc/lbessel_fastmath.hpp), in units in the last
+(lbessel_elementary_f64: the hardware reciprocal and inverse square root with
+two Newton steps each, the exp and log sequences of csrc/lbessel_fastmath.hpp), in units in the last
 place against 60-digit references from Python's decimal module."""
 import math
 from decimal import Decimal, localcontext
@@ -27,6 +27,8 @@ def _ref(op, a):
         d = Decimal(a)
         if op == "rcp":
             return 1 / d
+        if op == "rsqrt":
+            return 1 / d.sqrt()
         if op in ("exp", "exp_bounded"):
             return d.exp()
         if op == "log":
@@ -53,6 +55,17 @@ def test_reciprocal_within_one_ulp(lb):
                          g.uniform(0.5, 2.0, 1000), (k * k)[:, None].ravel() - g.uniform(0, 0.25, 40),
                          [1.0, 2.0, 3.0, 0.1, 1e-300, 1e300]])
     assert _worst(lb, "rcp", xs) <= 1.0
+
+
+def test_inverse_square_root_within_one_ulp(lb):
+    """The Debye branch's 1/sqrt(v^2 + x^2): arguments from 1e-2 (v > 0.1) to
+    2e300, around powers of two and exact squares."""
+    g = np.random.default_rng(16)
+    k = np.arange(1.0, 41.0)
+    xs = np.concatenate([10.0 ** g.uniform(-2, 300, 3000), g.uniform(0.5, 4.0, 1000),
+                         k * k, np.nextafter(k * k, 0), np.nextafter(k * k, 2e3),
+                         [1.0, 2.0, 4.0, 0.01, 2e300]])
+    assert _worst(lb, "rsqrt", xs) <= 1.0
 
 
 @pytest.mark.parametrize("op", ["exp", "exp_bounded"])
