@@ -454,10 +454,13 @@ template <typename T>
 __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     const T hx = T(0.5) * x;
     const T q = hx * hx;
-    // two terms per step with one reciprocal: a_k/a_{k-1} = q / d_k,
-    // d_k = k (k + v), so a_k = a_{k-1} q d_{k+1} / (d_k d_{k+1}) and
-    // a_{k+1} = a_{k-1} q^2 / (d_k d_{k+1}).  The stop test runs on the second
-    // term of a pair, so at most one term more than a per-term test is summed.
+    // four terms per step with one reciprocal: a_k/a_{k-1} = q / d_k,
+    // d_k = k (k + v), so with R = 1/(d_k d_{k+1} d_{k+2} d_{k+3}) the pair
+    // reciprocals are 1/(d_k d_{k+1}) = R d_{k+2} d_{k+3} and 1/(d_{k+2} d_{k+3})
+    // = R d_k d_{k+1}; a_k = a_{k-1} q d_{k+1} / (d_k d_{k+1}) and
+    // a_{k+1} = a_{k-1} q^2 / (d_k d_{k+1}), and likewise for the second pair.
+    // The stop test runs on the last term of a step, so at most three terms
+    // more than a per-term test are summed.
     // The sum is kept without its leading 1 (sum of a_k / a_0 over k >= 1)
     // and enters through log1p: where I_v(x) is close to (x/2)^v / Gamma(v+1)
     // (small x) its log stays accurate relative to the small correction.
@@ -465,19 +468,26 @@ __device__ __forceinline__ T br_series_i(T v, T x, const LgTab *lt) {
     const T q_2 = T(2) * q;
     T term = T(1);
     T sum = T(0);
-    T f0 = T(-1);
-    for (int k = 1; k < 200; k += 2) {
-        f0 += T(2);
-        const T f1 = f0 + T(1);
+    T f0 = T(-3);
+    for (int k = 1; k < 200; k += 4) {
+        f0 += T(4);
+        const T f1 = f0 + T(1), f2 = f0 + T(2), f3 = f0 + T(3);
         const T d0 = f0 * (f0 + v);
         const T d1 = f1 * (f1 + v);
-        const T r = lrcp(d0 * d1);
-        const T t0 = term * q * d1 * r;
-        term = term * q2 * r;
+        const T d2 = f2 * (f2 + v);
+        const T d3 = f3 * (f3 + v);
+        const T d01 = d0 * d1, d23 = d2 * d3;
+        const T r = lrcp(d01 * d23);
+        const T r01 = r * d23, r23 = r * d01;
+        const T t0 = term * q * d1 * r01;
+        const T t1 = term * q2 * r01;
+        const T t2 = t1 * q * d3 * r23;
+        term = t1 * q2 * r23;
         sum = sum + t0;
+        sum = sum + t1;
+        sum = sum + t2;
         sum = sum + term;
-        // both conditions without a short circuit: one branch per pair
-        if ((d1 > q_2) & (term < fma(Cst<T>::series_eps, sum, Cst<T>::series_eps)))
+        if ((d3 > q_2) & (term < fma(Cst<T>::series_eps, sum, Cst<T>::series_eps)))
             break;
     }
     T lg;
